@@ -1,0 +1,187 @@
+/*
+ * rwpt.h -- C ABI of the MI355X (gfx950) library for the particle-to-particle
+ * mass-transfer step of interacting random-walk particle tracking
+ * (Engdahl, Schmidt & Benson, arXiv:1811.05474).
+ *
+ * One call of rwpt_step advances every realisation of an ensemble by n steps.
+ * A step is, in this order (Sec. 1.1 and Sec. 7 of the paper):
+ *   1. the random-walk move of Eq. (1)/(2) at zero velocity,
+ *      x <- x + sqrt(2 D_rw dt) dW, with reflection at the zero-flux box walls
+ *      (Sec. 3); D_rw = rw_ratio * D (the "mixed" diffusion split of Sec. 2.2
+ *      and Sec. 3, where each operation applies half of the total);
+ *   2. the neighbour search: every pair with separation within the cutoff
+ *      s_max = kappa * sigma, sigma = sqrt(8 D dt) (Sec. 2.1, Sec. 2.2);
+ *   3. the co-location weights w_ij = exp(-s_ij^2 / (8 D dt)) of Eq. (3), their
+ *      normalisation (Sec. 1.1, after Eq. 3) and the explicit exchange of
+ *      Eqs. (4) and (6) for every species, from beginning-of-step masses and
+ *      positions (the "matrix explicit" scheme of Sec. 1.1);
+ *   4. the irreversible reaction A + B -> 0 evaluated per particle after the
+ *      transfer (Sec. 3, Sec. 7), and an FP64 audit of the species totals and
+ *      of sum(A - B), which the transfer and the reaction both conserve.
+ *
+ * Conventions
+ *   - Every call returns an rwpt_status; nothing aborts or exits.  On error the
+ *     context is left as it was and rwpt_last_error() describes the failure.
+ *   - Host arrays are read (init) or written (query) in the caller's particle
+ *     order: particle i of realisation r has global index off_r + i where off_r
+ *     is the sum of the sizes of realisations 0..r-1.
+ *   - Positions are N x dim row-major doubles (pos[i*dim + k]); masses are
+ *     species-major doubles (mass[s*N + i]).  In the FP32 form they are rounded
+ *     to binary32 on entry and widened exactly on exit.
+ *   - The context owns all device memory.  A context is used by one host thread
+ *     at a time; several contexts may share a device.
+ *   - Work is queued on the configured HIP stream; rwpt_step returns before the
+ *     GPU finishes.  Query and audit calls synchronise that stream.
+ */
+#ifndef RWPT_H
+#define RWPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RWPT_OK = 0,
+  RWPT_EINVAL = -1,      /* invalid argument or configuration */
+  RWPT_ENOMEM = -2,      /* host or device allocation failed */
+  RWPT_EDEVICE = -3,     /* HIP runtime error, or no usable gfx950 device */
+  RWPT_ESTATE = -4,      /* call not valid in the current state (e.g. step before init) */
+  RWPT_EUNSUPPORTED = -5 /* valid but not supported combination */
+} rwpt_status;
+
+enum { RWPT_FP32 = 0, RWPT_FP64 = 1 };
+
+/* Normalisation of the co-location weights (Sec. 1.1, after Eq. 3).
+ * SYM: P_ij = (w_ij / r_i + w_ij / r_j) / 2 with r_i = sum_j w_ij -- the
+ *      symmetric part of the paper's row-normalised P; every pair exchange is
+ *      antisymmetric, so species mass is conserved (the conservation
+ *      requirement of Sec. 6).  Default.
+ * ROW: P_ij = w_ij / r_i exactly as printed; not conservative when
+ *      neighbourhoods differ. */
+enum { RWPT_NORM_SYM = 0, RWPT_NORM_ROW = 1 };
+
+/* Evaluation path.  SPARSE: cell-list neighbour search + per-pair kernels.
+ * DENSE: every pair of a realisation on matrix cores (the full-matrix
+ * "brute force" of Sec. 1.1); needs kappa = +inf and dim = 1.
+ * AUTO: DENSE when allowed and kappa is infinite, else SPARSE. */
+enum { RWPT_PATH_AUTO = 0, RWPT_PATH_SPARSE = 1, RWPT_PATH_DENSE = 2 };
+
+typedef struct rwpt_config {
+  int32_t dim;            /* 1, 2 or 3 */
+  int32_t n_species;      /* S, 1..8 */
+  int32_t react_a;        /* species index of A in A + B -> 0, or -1 (no reaction) */
+  int32_t react_b;        /* species index of B, or -1 */
+  double box_lo[3];       /* reflecting walls; entries beyond dim ignored */
+  double box_hi[3];
+  double kappa;           /* cutoff in units of sigma; > 0; INFINITY = every pair */
+  double rw_ratio;        /* D_rw = rw_ratio * D; 0 = positions never move */
+  int32_t precision;      /* RWPT_FP32 or RWPT_FP64 */
+  int32_t norm;           /* RWPT_NORM_SYM or RWPT_NORM_ROW */
+  int32_t path;           /* RWPT_PATH_* */
+  int32_t tile_lanes;     /* lanes sharing one particle in the pair kernels: 1, 4, 8 or 16;
+                             0 = choose from dim */
+  double cell_refine[3];  /* cells per cutoff length along each axis (> 0); 0 = choose */
+  int32_t device;         /* HIP device ordinal */
+  int32_t use_graph;      /* 1 = replay each rwpt_step as one captured HIP graph */
+  uint64_t seed;          /* key of the counter-based random walk */
+  void *stream;           /* hipStream_t to queue work on; NULL = a stream the context owns */
+} rwpt_config;
+
+typedef struct rwpt_ctx rwpt_ctx;
+
+/* Fill *cfg with defaults: dim 2, S 2, reaction (0, 1), unit box, kappa 3,
+ * rw_ratio 1, FP32, SYM, AUTO path, automatic tiling, device 0, graphs on,
+ * seed 0, NULL stream. */
+void rwpt_config_default(rwpt_config *cfg);
+
+/* Validate *cfg and create a context.  No device memory is touched until
+ * rwpt_init_ensemble.  *out receives NULL on failure except for RWPT_EINVAL
+ * where a context holding the error message may be returned (free it with
+ * rwpt_destroy); pass out == NULL-safe pointers only. */
+rwpt_status rwpt_create(const rwpt_config *cfg, rwpt_ctx **out);
+
+/* Load an ensemble of n_real independent realisations.
+ *   n_per_real[r] >= 0 particles each (host array, n_real entries; n_real >= 1);
+ *   pos:  host, N x dim row-major, N = sum n_per_real; every coordinate finite
+ *         and inside the closed box;
+ *   mass: host, S x N species-major, finite;
+ *   d_scale: host, n_real multipliers of the D given to rwpt_step (D_r = D *
+ *         d_scale[r]), each >= 0 and finite; NULL = all 1.
+ * Replaces any previous ensemble and resets the step counter to 0. */
+rwpt_status rwpt_init_ensemble(rwpt_ctx *ctx, int32_t n_real, const int64_t *n_per_real,
+                               const double *pos, const double *mass, const double *d_scale);
+
+/* Advance every realisation by n_steps >= 0 explicit steps of length dt > 0
+ * with mass-transfer diffusion D >= 0 (D_m of Eq. 3).  D * d_scale[r] = 0
+ * leaves realisation r's masses to the reaction only.  Asynchronous. */
+rwpt_status rwpt_step(rwpt_ctx *ctx, double dt, double D, int32_t n_steps);
+
+/* Wait for all queued work of the context. */
+rwpt_status rwpt_sync(rwpt_ctx *ctx);
+
+/* Copy the current masses (S x N species-major, caller's order) to host memory. */
+rwpt_status rwpt_query_masses(rwpt_ctx *ctx, double *mass_out);
+
+/* Copy the current positions (N x dim row-major, caller's order) to host memory. */
+rwpt_status rwpt_query_positions(rwpt_ctx *ctx, double *pos_out);
+
+/* FP64 audit of the current state, n_real x (S + 1) doubles:
+ * out[r*(S+1) + s] = sum_i M_s of realisation r, out[r*(S+1) + S] =
+ * sum_i (M_a - M_b) (0 without a reaction).  After init it reports the loaded
+ * values; after a step, the values the device computed at the end of it. */
+rwpt_status rwpt_audit(rwpt_ctx *ctx, double *out);
+
+/* Number of steps taken since init. */
+rwpt_status rwpt_steps_taken(rwpt_ctx *ctx, int64_t *out);
+
+/* Count, for the current positions and the cutoff of (dt, D), the ordered
+ * neighbour pairs j != i within the cutoff (pairs_out, summed over
+ * realisations) and the candidate evaluations the sparse kernels perform
+ * (evals_out, may be NULL).  Synchronous; does not change the state. */
+rwpt_status rwpt_count_pairs(rwpt_ctx *ctx, double dt, double D, int64_t *pairs_out,
+                             int64_t *evals_out);
+
+/* Debug export of the neighbour lists for the cutoff of (dt, D) and the
+ * current positions, as CSR over the caller's particle order with ascending
+ * global column indices, j = i included.  Call with cols == NULL to get the
+ * number of entries in *nnz_out; then with rowptr (N + 1 int64) and cols
+ * (*nnz_out int32) allocated.  Synchronous; does not change the state. */
+rwpt_status rwpt_neighbors(rwpt_ctx *ctx, double dt, double D, int64_t *rowptr, int32_t *cols,
+                           int64_t *nnz_out);
+
+/* Per-phase timing.  While enabled, rwpt_step launches eagerly (no graph) and
+ * brackets each kernel phase with HIP events on the context's stream.
+ * rwpt_profile_read returns, per phase p < n_phases (at most 16), the summed
+ * milliseconds ms[p] and launch counts cnt[p] since the last reset, and the
+ * phase names through rwpt_profile_phase_name. */
+rwpt_status rwpt_profile_enable(rwpt_ctx *ctx, int32_t on);
+rwpt_status rwpt_profile_reset(rwpt_ctx *ctx);
+rwpt_status rwpt_profile_read(rwpt_ctx *ctx, double *ms, int64_t *cnt, int32_t *n_phases);
+const char *rwpt_profile_phase_name(int32_t phase);
+
+/* Current tiling: tile_lanes and the per-axis cell refinement in use. */
+rwpt_status rwpt_get_tiling(rwpt_ctx *ctx, int32_t *tile_lanes, double *cell_refine3);
+
+/* Autotune the sparse kernels for (dt, D): time every candidate tiling for
+ * trial_steps steps on a snapshot of the current state, keep the fastest and
+ * restore the state (masses, positions, step counter).  Results are cached in
+ * the file named by the environment variable RWPT_TUNE_CACHE if it is set. */
+rwpt_status rwpt_autotune(rwpt_ctx *ctx, double dt, double D, int32_t trial_steps);
+
+/* Message of the last failed call on this context ("" if none).  Valid until
+ * the next call on the context. */
+const char *rwpt_last_error(const rwpt_ctx *ctx);
+
+/* Library version string. */
+const char *rwpt_version(void);
+
+/* Release all resources.  NULL is allowed. */
+void rwpt_destroy(rwpt_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RWPT_H */

@@ -1,0 +1,959 @@
+// rwpt_api.hip -- host side of the C ABI declared in include/rwpt.h.
+//
+// Owns the device state of an ensemble, builds the per-realisation cell grid
+// and neighbour-row stencil for a given (dt, D), sequences the kernels of one
+// explicit step (optionally replayed as a captured HIP graph) and converts
+// between the caller's particle order and the cell-sorted device order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rwpt.h"
+#include "rwpt_kernels.h"
+
+using namespace rwpt;
+
+namespace {
+
+thread_local std::string g_err;  // errors raised before a context exists
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t b) {
+    if (b == 0) b = 256;
+    if (p && b <= bytes) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return e;
+    }
+    bytes = b;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+const char* kPhaseNames[PH_N] = {"walk_key", "cell_scan", "scatter", "canon", "rowsum",
+                                 "exchange", "audit",     "dense",   "count"};
+
+}  // namespace
+
+struct rwpt_ctx {
+  rwpt_config cfg;
+  std::string err;
+  bool device_ready = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+
+  bool initialized = false;
+  int64_t N = 0;
+  int32_t n_real = 0;
+  int S = 0, dim = 0;
+  size_t tsize = 4;
+  int64_t cap = 0;
+  std::vector<int64_t> real_start;
+  std::vector<double> d_scale;
+
+  DevBuf pos0, pos1, mass0, mass1, id, key, slot, tmp_src, tmp_id, tmp_key, skey, r, q;
+  DevBuf cell_count, cell_start, scan_part;
+  DevBuf d_rp, d_st, d_tiles, d_tile_start, d_real_start;
+  DevBuf audit_part, audit_out, step_ctr, counts;
+  int64_t ncell_total = 0;
+
+  std::vector<RealParams> h_rp;
+  std::vector<StencilRow> h_st;
+  std::vector<Tile> h_tiles;
+  std::vector<int32_t> h_tile_start;
+  int32_t ntiles = 0;
+  int log2l = 3;
+  double refine[3] = {0, 0, 0};
+
+  bool grid_valid = false;
+  double g_dt = 0.0, g_D = 0.0;
+  bool sorted_valid = false;
+  int64_t steps = 0;
+  std::vector<double> audit_init;
+
+  hipGraphExec_t gx[2] = {nullptr, nullptr};  // [0] = step with sort, [1] = without
+
+  bool prof = false;
+  struct Ev {
+    hipEvent_t a, b;
+    int ph;
+  };
+  std::vector<Ev> ev_pending;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[PH_N] = {0};
+  int64_t prof_cnt[PH_N] = {0};
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+static rwpt_status fail(rwpt_ctx* c, rwpt_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  else g_err = buf;
+  return st;
+}
+
+#define HIPCHK(c, expr)                                                                     \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      (void)hipGetLastError();                                                              \
+      return fail((c), e_ == hipErrorOutOfMemory ? RWPT_ENOMEM : RWPT_EDEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                        \
+    }                                                                                       \
+  } while (0)
+
+static int lanes_to_log2(int lanes) {
+  switch (lanes) {
+    case 1: return 0;
+    case 4: return 2;
+    case 8: return 3;
+    case 16: return 4;
+    default: return -1;
+  }
+}
+
+static void default_refine(int dim, double out[3]) {
+  // cells per cutoff length: fine along x (the fastest key axis, which trims
+  // the candidate ranges), about one cutoff across the other axes
+  if (dim == 1) {
+    out[0] = 8.0; out[1] = 1.0; out[2] = 1.0;
+  } else if (dim == 2) {
+    out[0] = 4.0; out[1] = 2.0; out[2] = 1.0;
+  } else {
+    out[0] = 2.0; out[1] = 1.0; out[2] = 1.0;
+  }
+}
+
+static void invalidate_graphs(rwpt_ctx* c) {
+  for (int k = 0; k < 2; ++k)
+    if (c->gx[k]) {
+      (void)hipGraphExecDestroy(c->gx[k]);
+      c->gx[k] = nullptr;
+    }
+}
+
+static rwpt_status ensure_device(rwpt_ctx* c) {
+  if (c->device_ready) return RWPT_OK;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return fail(c, RWPT_EDEVICE, "no HIP device available (%s)",
+                e != hipSuccess ? hipGetErrorString(e) : "device count 0");
+  }
+  if (c->cfg.device >= n) return fail(c, RWPT_EDEVICE, "device %d not present (%d devices)", c->cfg.device, n);
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  hipDeviceProp_t prop;
+  HIPCHK(c, hipGetDeviceProperties(&prop, c->cfg.device));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(c, RWPT_EDEVICE, "device %d is %s; this library is built for gfx950", c->cfg.device,
+                prop.gcnArchName);
+  if (c->cfg.stream) {
+    c->stream = (hipStream_t)c->cfg.stream;
+    c->own_stream = false;
+  } else {
+    HIPCHK(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  HIPCHK(c, c->step_ctr.ensure(sizeof(uint64_t)));
+  c->device_ready = true;
+  return RWPT_OK;
+}
+
+// Record a phase: start event before a launch, stop event after it.
+struct PhaseScope {
+  rwpt_ctx* c;
+  int ph;
+  hipEvent_t a = nullptr, b = nullptr;
+  PhaseScope(rwpt_ctx* cc, int p) : c(cc), ph(p) {
+    if (!c->prof) return;
+    a = take();
+    b = take();
+    if (a) (void)hipEventRecord(a, c->stream);
+  }
+  hipEvent_t take() {
+    if (!c->ev_pool.empty()) {
+      hipEvent_t e = c->ev_pool.back();
+      c->ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~PhaseScope() {
+    if (!c->prof || !a || !b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->ev_pending.push_back({a, b, ph});
+  }
+};
+
+static void drain_profile(rwpt_ctx* c) {
+  if (c->ev_pending.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& ev : c->ev_pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
+      c->prof_ms[ev.ph] += ms;
+      c->prof_cnt[ev.ph] += 1;
+    }
+    c->ev_pool.push_back(ev.a);
+    c->ev_pool.push_back(ev.b);
+  }
+  c->ev_pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// grid, stencil and tiles for (dt, D)
+// ---------------------------------------------------------------------------
+
+static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
+  if (c->grid_valid && c->g_dt == dt && c->g_D == D) return RWPT_OK;
+  const rwpt_config& cfg = c->cfg;
+  const int dim = c->dim;
+  int lanes = cfg.tile_lanes ? cfg.tile_lanes : 8;
+  c->log2l = lanes_to_log2(lanes);
+  double defr[3];
+  default_refine(dim, defr);
+  for (int k = 0; k < 3; ++k) c->refine[k] = cfg.cell_refine[k] > 0 ? cfg.cell_refine[k] : defr[k];
+  const int G = 64 >> c->log2l;
+
+  c->h_rp.assign(c->n_real, RealParams{});
+  c->h_st.clear();
+  c->h_tiles.clear();
+  c->h_tile_start.assign(c->n_real + 1, 0);
+  int64_t cell_off = 0;
+  for (int r = 0; r < c->n_real; ++r) {
+    RealParams& P = c->h_rp[r];
+    memset(&P, 0, sizeof(P));
+    double L[3];
+    for (int k = 0; k < 3; ++k) {
+      P.lo[k] = k < dim ? cfg.box_lo[k] : 0.0;
+      P.hi[k] = k < dim ? cfg.box_hi[k] : 1.0;
+      L[k] = P.hi[k] - P.lo[k];
+    }
+    P.p_begin = c->real_start[r];
+    P.p_end = c->real_start[r + 1];
+    const int64_t nr = P.p_end - P.p_begin;
+    const double Dr = D * c->d_scale[r];
+    P.amp = cfg.rw_ratio > 0.0 ? std::sqrt(2.0 * (cfg.rw_ratio * Dr) * dt) : 0.0;
+    P.active = Dr > 0.0 ? 1 : 0;
+    int64_t nc[3] = {1, 1, 1};
+    double rcg = 0.0;
+    if (P.active) {
+      const double sigma2 = 8.0 * Dr * dt;
+      const double rc2 = std::isinf(cfg.kappa) ? INFINITY : cfg.kappa * cfg.kappa * sigma2;
+      P.rc2_d = rc2;
+      P.rc2_f = (float)rc2;
+      P.escale_d = -1.0 / sigma2;
+      P.escale_f = (float)(-1.4426950408889634073599246810019 / sigma2);
+      // geometric cutoff: covers the rounding of s^2 in the predicate
+      rcg = std::sqrt(rc2) * (1.0 + 1e-5);
+      if (std::isfinite(rcg)) {
+        for (int k = 0; k < dim; ++k) {
+          double v = std::floor(L[k] * c->refine[k] / rcg);
+          if (!(v >= 1.0)) v = 1.0;
+          if (v > (double)(1 << 20)) v = (double)(1 << 20);
+          nc[k] = (int64_t)v;
+        }
+        const int64_t cap_cells = std::max<int64_t>(4 * nr, 64);
+        for (;;) {
+          int64_t prod = nc[0] * nc[1] * nc[2];
+          if (prod <= cap_cells) break;
+          int kmax = 0;
+          for (int k = 1; k < 3; ++k)
+            if (nc[k] > nc[kmax]) kmax = k;
+          if (nc[kmax] <= 1) break;
+          nc[kmax] = (nc[kmax] + 1) / 2;
+        }
+      }
+    }
+    for (int k = 0; k < 3; ++k) {
+      P.nc[k] = (int32_t)nc[k];
+      P.inv_h[k] = (double)nc[k] / L[k];
+    }
+    P.cell_off = cell_off;
+    cell_off += nc[0] * nc[1] * nc[2];
+    P.stencil_off = (int32_t)c->h_st.size();
+    if (P.active) {
+      const double h[3] = {L[0] / nc[0], L[1] / nc[1], L[2] / nc[2]};
+      int Ry = 0, Rz = 0;
+      if (dim >= 2) Ry = std::isfinite(rcg) ? (int)std::min<double>(nc[1] - 1, std::ceil(rcg / h[1])) : (int)nc[1] - 1;
+      if (dim >= 3) Rz = std::isfinite(rcg) ? (int)std::min<double>(nc[2] - 1, std::ceil(rcg / h[2])) : (int)nc[2] - 1;
+      for (int dz = -Rz; dz <= Rz; ++dz)
+        for (int dy = -Ry; dy <= Ry; ++dy) {
+          int rx;
+          if (std::isfinite(rcg)) {
+            const double ym = std::max(0, std::abs(dy) - 1) * h[1];
+            const double zm = std::max(0, std::abs(dz) - 1) * h[2];
+            const double rem = rcg * rcg - ym * ym - zm * zm;
+            if (rem < 0.0) continue;
+            const double hw = std::sqrt(rem);
+            rx = (int)std::min<double>(nc[0] - 1, std::ceil(hw * P.inv_h[0]));
+          } else {
+            rx = (int)nc[0] - 1;
+          }
+          c->h_st.push_back(StencilRow{dy, dz, rx, 0});
+        }
+    }
+    P.n_stencil = (int32_t)c->h_st.size() - P.stencil_off;
+    c->h_tile_start[r] = (int32_t)c->h_tiles.size();
+    for (int64_t b = P.p_begin; b < P.p_end; b += G)
+      c->h_tiles.push_back(Tile{(int32_t)b, (int32_t)std::min<int64_t>(b + G, P.p_end), r, 0});
+  }
+  c->h_tile_start[c->n_real] = (int32_t)c->h_tiles.size();
+  if (cell_off >= (int64_t)1 << 31) return fail(c, RWPT_EUNSUPPORTED, "cell grid too large (%lld cells)", (long long)cell_off);
+  c->ntiles = (int32_t)c->h_tiles.size();
+
+  // device copies
+  const int64_t ncell = cell_off;
+  const int64_t nscan = (ncell + kScanChunk - 1) / kScanChunk + 1;
+  bool regrow = (size_t)(ncell * 4) > c->cell_count.bytes;
+  HIPCHK(c, c->cell_count.ensure((size_t)ncell * 4));
+  HIPCHK(c, c->cell_start.ensure((size_t)(ncell + 1) * 4));
+  HIPCHK(c, c->scan_part.ensure((size_t)nscan * 4));
+  HIPCHK(c, c->d_rp.ensure(c->h_rp.size() * sizeof(RealParams)));
+  HIPCHK(c, c->d_st.ensure(std::max<size_t>(1, c->h_st.size()) * sizeof(StencilRow)));
+  HIPCHK(c, c->d_tiles.ensure(std::max<size_t>(1, c->h_tiles.size()) * sizeof(Tile)));
+  HIPCHK(c, c->d_tile_start.ensure(c->h_tile_start.size() * sizeof(int32_t)));
+  HIPCHK(c, c->audit_part.ensure((size_t)std::max(1, c->ntiles) * (c->S + 1) * sizeof(double)));
+  HIPCHK(c, c->counts.ensure((size_t)std::max(1, c->ntiles) * 2 * sizeof(unsigned long long)));
+  HIPCHK(c, hipMemcpyAsync(c->d_rp.p, c->h_rp.data(), c->h_rp.size() * sizeof(RealParams),
+                           hipMemcpyHostToDevice, c->stream));
+  if (!c->h_st.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d_st.p, c->h_st.data(), c->h_st.size() * sizeof(StencilRow),
+                             hipMemcpyHostToDevice, c->stream));
+  if (!c->h_tiles.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d_tiles.p, c->h_tiles.data(), c->h_tiles.size() * sizeof(Tile),
+                             hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_tile_start.p, c->h_tile_start.data(),
+                           c->h_tile_start.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  (void)regrow;
+  HIPCHK(c, hipMemsetAsync(c->cell_count.p, 0, (size_t)ncell * 4, c->stream));
+  // the host vectors above must stay alive until the copies finish
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->ncell_total = ncell;
+  c->grid_valid = true;
+  c->g_dt = dt;
+  c->g_D = D;
+  c->sorted_valid = false;
+  invalidate_graphs(c);
+  return RWPT_OK;
+}
+
+static PairArgs pair_args(rwpt_ctx* c) {
+  PairArgs a;
+  memset(&a, 0, sizeof(a));
+  a.pos = c->pos0.p;
+  a.cap = c->cap;
+  a.mass_in = c->mass1.p;
+  a.mass_out = c->mass0.p;
+  a.q_in = c->q.p;
+  a.q_out = c->q.p;
+  a.r_out = c->r.as<double>();
+  a.skey = c->skey.as<uint32_t>();
+  a.cell_start = c->cell_start.as<uint32_t>();
+  a.tiles = c->d_tiles.as<Tile>();
+  a.ntiles = c->ntiles;
+  a.rp = c->d_rp.as<RealParams>();
+  a.st = c->d_st.as<StencilRow>();
+  a.S = c->S;
+  a.react_a = c->cfg.react_a;
+  a.react_b = c->cfg.react_b;
+  a.norm = c->cfg.norm;
+  a.audit_part = c->audit_part.as<double>();
+  a.counts = c->counts.as<unsigned long long>();
+  return a;
+}
+
+// Sort into the cell grid: [walk] -> key -> counting sort -> canonical order.
+// Leaves positions in pos0, masses in mass1, ids in id, keys in skey.
+static rwpt_status enqueue_sort(rwpt_ctx* c, bool walk) {
+  const int fp64 = c->cfg.precision == RWPT_FP64;
+  const int32_t n = (int32_t)c->N;
+  {
+    PhaseScope ps(c, PH_WALK_KEY);
+    HIPCHK(c, launch_walk_key(fp64, c->dim, c->pos0.p, c->pos1.p, c->cap, c->id.as<uint32_t>(), n,
+                              c->d_rp.as<RealParams>(), c->d_real_start.as<int64_t>(), c->n_real,
+                              c->step_ctr.as<uint64_t>(), c->cfg.seed, walk ? 1 : 0,
+                              c->cell_count.as<uint32_t>(), c->key.as<uint32_t>(),
+                              c->slot.as<uint32_t>(), c->stream));
+  }
+  {
+    PhaseScope ps(c, PH_SCAN);
+    HIPCHK(c, launch_cell_scan(c->cell_count.as<uint32_t>(), c->cell_start.as<uint32_t>(), c->ncell_total,
+                               c->scan_part.as<uint32_t>(), c->stream));
+  }
+  {
+    PhaseScope ps(c, PH_SCATTER);
+    HIPCHK(c, launch_scatter(n, c->key.as<uint32_t>(), c->slot.as<uint32_t>(), c->cell_start.as<uint32_t>(),
+                             c->id.as<uint32_t>(), c->tmp_src.as<uint32_t>(), c->tmp_id.as<uint32_t>(),
+                             c->tmp_key.as<uint32_t>(), c->stream));
+  }
+  {
+    PhaseScope ps(c, PH_CANON);
+    HIPCHK(c, launch_canon(fp64, c->dim, n, c->tmp_src.as<uint32_t>(), c->tmp_id.as<uint32_t>(),
+                           c->tmp_key.as<uint32_t>(), c->cell_start.as<uint32_t>(), c->pos1.p, c->pos0.p,
+                           c->cap, c->mass0.p, c->mass1.p, c->S, c->id.as<uint32_t>(),
+                           c->skey.as<uint32_t>(), c->stream));
+  }
+  return RWPT_OK;
+}
+
+// One explicit step.  Masses start and end in mass0; positions in pos0.
+static rwpt_status enqueue_step(rwpt_ctx* c, bool sort, bool walk) {
+  const int fp64 = c->cfg.precision == RWPT_FP64;
+  if (sort) {
+    rwpt_status st = enqueue_sort(c, walk);
+    if (st != RWPT_OK) return st;
+  } else {
+    HIPCHK(c, hipMemcpyAsync(c->mass1.p, c->mass0.p, (size_t)c->S * c->cap * c->tsize,
+                             hipMemcpyDeviceToDevice, c->stream));
+  }
+  PairArgs a = pair_args(c);
+  if (c->cfg.norm == RWPT_NORM_SYM) {
+    PhaseScope ps(c, PH_ROWSUM);
+    HIPCHK(c, launch_rowsum(fp64, c->dim, c->log2l, a, c->stream));
+  }
+  {
+    PhaseScope ps(c, PH_EXCHANGE);
+    HIPCHK(c, launch_exchange(fp64, c->dim, c->log2l, a, c->stream));
+  }
+  {
+    PhaseScope ps(c, PH_AUDIT);
+    HIPCHK(c, launch_audit_reduce(c->audit_part.as<double>(), c->S + 1, c->d_tile_start.as<int32_t>(),
+                                  c->n_real, c->audit_out.as<double>(), c->step_ctr.as<uint64_t>(), 1,
+                                  c->stream));
+  }
+  return RWPT_OK;
+}
+
+static rwpt_status ensure_sorted(rwpt_ctx* c) {
+  if (c->sorted_valid) return RWPT_OK;
+  rwpt_status st = enqueue_sort(c, false);
+  if (st != RWPT_OK) return st;
+  // enqueue_sort leaves masses in mass1; bring them back to mass0
+  HIPCHK(c, hipMemcpyAsync(c->mass0.p, c->mass1.p, (size_t)c->S * c->cap * c->tsize,
+                           hipMemcpyDeviceToDevice, c->stream));
+  c->sorted_valid = true;
+  return RWPT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* rwpt_version(void) { return "rwpt-mi355x 0.1 (gfx950)"; }
+
+void rwpt_config_default(rwpt_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->dim = 2;
+  cfg->n_species = 2;
+  cfg->react_a = 0;
+  cfg->react_b = 1;
+  for (int k = 0; k < 3; ++k) {
+    cfg->box_lo[k] = 0.0;
+    cfg->box_hi[k] = 1.0;
+  }
+  cfg->kappa = 3.0;
+  cfg->rw_ratio = 1.0;
+  cfg->precision = RWPT_FP32;
+  cfg->norm = RWPT_NORM_SYM;
+  cfg->path = RWPT_PATH_AUTO;
+  cfg->tile_lanes = 0;
+  cfg->device = 0;
+  cfg->use_graph = 1;
+  cfg->seed = 0;
+  cfg->stream = nullptr;
+}
+
+rwpt_status rwpt_create(const rwpt_config* cfg, rwpt_ctx** out) {
+  if (!out) return fail(nullptr, RWPT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(nullptr, RWPT_EINVAL, "cfg is NULL");
+  const rwpt_config& c = *cfg;
+  if (c.dim < 1 || c.dim > 3) return fail(nullptr, RWPT_EINVAL, "dim must be 1, 2 or 3 (got %d)", c.dim);
+  if (c.n_species < 1 || c.n_species > 8)
+    return fail(nullptr, RWPT_EINVAL, "n_species must be in 1..8 (got %d)", c.n_species);
+  const bool ra = c.react_a >= 0, rb = c.react_b >= 0;
+  if (ra != rb || c.react_a < -1 || c.react_b < -1)
+    return fail(nullptr, RWPT_EINVAL, "react_a/react_b must both be -1 or both valid species");
+  if (ra && (c.react_a >= c.n_species || c.react_b >= c.n_species || c.react_a == c.react_b))
+    return fail(nullptr, RWPT_EINVAL, "reaction species (%d, %d) invalid for S = %d", c.react_a,
+                c.react_b, c.n_species);
+  for (int k = 0; k < c.dim; ++k)
+    if (!std::isfinite(c.box_lo[k]) || !std::isfinite(c.box_hi[k]) || !(c.box_lo[k] < c.box_hi[k]))
+      return fail(nullptr, RWPT_EINVAL, "box axis %d must satisfy finite lo < hi", k);
+  if (!(c.kappa > 0.0)) return fail(nullptr, RWPT_EINVAL, "kappa must be > 0 (or INFINITY)");
+  if (!std::isfinite(c.rw_ratio) || c.rw_ratio < 0.0)
+    return fail(nullptr, RWPT_EINVAL, "rw_ratio must be finite and >= 0");
+  if (c.precision != RWPT_FP32 && c.precision != RWPT_FP64)
+    return fail(nullptr, RWPT_EINVAL, "precision must be RWPT_FP32 or RWPT_FP64");
+  if (c.norm != RWPT_NORM_SYM && c.norm != RWPT_NORM_ROW)
+    return fail(nullptr, RWPT_EINVAL, "norm must be RWPT_NORM_SYM or RWPT_NORM_ROW");
+  if (c.path < RWPT_PATH_AUTO || c.path > RWPT_PATH_DENSE)
+    return fail(nullptr, RWPT_EINVAL, "path must be AUTO, SPARSE or DENSE");
+  if (c.path == RWPT_PATH_DENSE)
+    return fail(nullptr, RWPT_EUNSUPPORTED, "the dense path is not available in this build");
+  if (c.tile_lanes != 0 && lanes_to_log2(c.tile_lanes) < 0)
+    return fail(nullptr, RWPT_EINVAL, "tile_lanes must be 0, 1, 4, 8 or 16 (got %d)", c.tile_lanes);
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(c.cell_refine[k]) || c.cell_refine[k] < 0.0 || c.cell_refine[k] > 64.0)
+      return fail(nullptr, RWPT_EINVAL, "cell_refine[%d] must be in [0, 64]", k);
+  if (c.device < 0) return fail(nullptr, RWPT_EINVAL, "device must be >= 0");
+  if (c.use_graph != 0 && c.use_graph != 1) return fail(nullptr, RWPT_EINVAL, "use_graph must be 0 or 1");
+  rwpt_ctx* ctx = new (std::nothrow) rwpt_ctx();
+  if (!ctx) return fail(nullptr, RWPT_ENOMEM, "out of host memory");
+  ctx->cfg = c;
+  ctx->S = c.n_species;
+  ctx->dim = c.dim;
+  ctx->tsize = c.precision == RWPT_FP64 ? 8 : 4;
+  *out = ctx;
+  return RWPT_OK;
+}
+
+static double neumaier_sum(const std::vector<double>& v) {
+  double s = 0.0, comp = 0.0;
+  for (double x : v) {
+    const double t = s + x;
+    if (std::fabs(s) >= std::fabs(x)) comp += (s - t) + x;
+    else comp += (x - t) + s;
+    s = t;
+  }
+  return s + comp;
+}
+
+rwpt_status rwpt_init_ensemble(rwpt_ctx* c, int32_t n_real, const int64_t* n_per_real, const double* pos,
+                               const double* mass, const double* d_scale) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  c->err.clear();
+  if (n_real < 1) return fail(c, RWPT_EINVAL, "n_real must be >= 1");
+  if (!n_per_real) return fail(c, RWPT_EINVAL, "n_per_real is NULL");
+  int64_t N = 0;
+  for (int r = 0; r < n_real; ++r) {
+    if (n_per_real[r] < 0) return fail(c, RWPT_EINVAL, "n_per_real[%d] < 0", r);
+    N += n_per_real[r];
+    if (N > (int64_t)INT32_MAX - 64) return fail(c, RWPT_EINVAL, "too many particles");
+  }
+  const int dim = c->dim, S = c->S;
+  if (N > 0 && (!pos || !mass)) return fail(c, RWPT_EINVAL, "pos/mass is NULL");
+  for (int64_t i = 0; i < N; ++i)
+    for (int k = 0; k < dim; ++k) {
+      const double v = pos[i * dim + k];
+      if (!std::isfinite(v) || v < c->cfg.box_lo[k] || v > c->cfg.box_hi[k])
+        return fail(c, RWPT_EINVAL, "position of particle %lld axis %d (%g) is outside the box or not finite",
+                    (long long)i, k, v);
+    }
+  for (int64_t i = 0; i < N * S; ++i)
+    if (!std::isfinite(mass[i])) return fail(c, RWPT_EINVAL, "mass entry %lld is not finite", (long long)i);
+  if (d_scale)
+    for (int r = 0; r < n_real; ++r)
+      if (!std::isfinite(d_scale[r]) || d_scale[r] < 0.0)
+        return fail(c, RWPT_EINVAL, "d_scale[%d] must be finite and >= 0", r);
+  rwpt_status st = ensure_device(c);
+  if (st != RWPT_OK) return st;
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  invalidate_graphs(c);
+  c->initialized = false;
+  c->grid_valid = false;
+  c->sorted_valid = false;
+  c->N = N;
+  c->n_real = n_real;
+  c->real_start.assign(n_real + 1, 0);
+  for (int r = 0; r < n_real; ++r) c->real_start[r + 1] = c->real_start[r] + n_per_real[r];
+  c->d_scale.assign(n_real, 1.0);
+  if (d_scale)
+    for (int r = 0; r < n_real; ++r) c->d_scale[r] = d_scale[r];
+  c->cap = std::max<int64_t>(64, (N + 63) / 64 * 64);
+  const size_t ts = c->tsize, cap = (size_t)c->cap;
+  HIPCHK(c, c->pos0.ensure(dim * cap * ts));
+  HIPCHK(c, c->pos1.ensure(dim * cap * ts));
+  HIPCHK(c, c->mass0.ensure(S * cap * ts));
+  HIPCHK(c, c->mass1.ensure(S * cap * ts));
+  HIPCHK(c, c->id.ensure(cap * 4));
+  HIPCHK(c, c->key.ensure(cap * 4));
+  HIPCHK(c, c->slot.ensure(cap * 4));
+  HIPCHK(c, c->tmp_src.ensure(cap * 4));
+  HIPCHK(c, c->tmp_id.ensure(cap * 4));
+  HIPCHK(c, c->tmp_key.ensure(cap * 4));
+  HIPCHK(c, c->skey.ensure(cap * 4));
+  HIPCHK(c, c->r.ensure(cap * 8));
+  HIPCHK(c, c->q.ensure(cap * ts));
+  HIPCHK(c, c->d_real_start.ensure((n_real + 1) * sizeof(int64_t)));
+  HIPCHK(c, c->audit_out.ensure((size_t)n_real * (S + 1) * sizeof(double)));
+
+  // host staging: SoA in the path's precision
+  std::vector<unsigned char> hp(dim * cap * ts, 0), hm(S * cap * ts, 0);
+  std::vector<uint32_t> hid(cap, 0);
+  c->audit_init.assign((size_t)n_real * (S + 1), 0.0);
+  std::vector<double> rounded_mass((size_t)N * S);
+  for (int64_t i = 0; i < N; ++i) {
+    hid[i] = (uint32_t)i;
+    for (int k = 0; k < dim; ++k) {
+      const double v = pos[i * dim + k];
+      if (ts == 8) ((double*)hp.data())[k * cap + i] = v;
+      else ((float*)hp.data())[k * cap + i] = (float)v;
+    }
+    for (int s = 0; s < S; ++s) {
+      const double v = mass[(size_t)s * N + i];
+      double vr;
+      if (ts == 8) {
+        ((double*)hm.data())[s * cap + i] = v;
+        vr = v;
+      } else {
+        const float f = (float)v;
+        ((float*)hm.data())[s * cap + i] = f;
+        vr = (double)f;
+      }
+      rounded_mass[(size_t)s * N + i] = vr;
+    }
+  }
+  for (int r = 0; r < n_real; ++r) {
+    const int64_t b = c->real_start[r], e = c->real_start[r + 1];
+    std::vector<double> acc;
+    for (int s = 0; s < S; ++s) {
+      acc.assign(rounded_mass.begin() + (size_t)s * N + b, rounded_mass.begin() + (size_t)s * N + e);
+      c->audit_init[(size_t)r * (S + 1) + s] = neumaier_sum(acc);
+    }
+    if (c->cfg.react_a >= 0) {
+      acc.clear();
+      for (int64_t i = b; i < e; ++i) {
+        acc.push_back(rounded_mass[(size_t)c->cfg.react_a * N + i]);
+        acc.push_back(-rounded_mass[(size_t)c->cfg.react_b * N + i]);
+      }
+      c->audit_init[(size_t)r * (S + 1) + S] = neumaier_sum(acc);
+    }
+  }
+  HIPCHK(c, hipMemcpyAsync(c->pos0.p, hp.data(), hp.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->mass0.p, hm.data(), hm.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->id.p, hid.data(), cap * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_real_start.p, c->real_start.data(), (n_real + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->step_ctr.p, 0, sizeof(uint64_t), c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->audit_out.p, c->audit_init.data(), c->audit_init.size() * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->steps = 0;
+  c->initialized = true;
+  return RWPT_OK;
+}
+
+rwpt_status rwpt_step(rwpt_ctx* c, double dt, double D, int32_t n_steps) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  c->err.clear();
+  if (!std::isfinite(dt) || dt <= 0.0) return fail(c, RWPT_EINVAL, "dt must be finite and > 0");
+  if (!std::isfinite(D) || D < 0.0) return fail(c, RWPT_EINVAL, "D must be finite and >= 0");
+  if (n_steps < 0) return fail(c, RWPT_EINVAL, "n_steps must be >= 0");
+  if (!c->initialized) return fail(c, RWPT_ESTATE, "rwpt_step before rwpt_init_ensemble");
+  if (n_steps == 0) return RWPT_OK;
+  if (c->N == 0) {
+    c->steps += n_steps;
+    return RWPT_OK;
+  }
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  rwpt_status st = build_grid(c, dt, D);
+  if (st != RWPT_OK) return st;
+  const bool walk = c->cfg.rw_ratio > 0.0 && D > 0.0;
+  for (int32_t it = 0; it < n_steps; ++it) {
+    const bool sort = walk || !c->sorted_valid;
+    if (c->cfg.use_graph && !c->prof) {
+      hipGraphExec_t& gx = c->gx[sort ? 0 : 1];
+      if (!gx) {
+        hipGraph_t g = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        rwpt_status s2 = enqueue_step(c, sort, walk);
+        hipError_t ec = hipStreamEndCapture(c->stream, &g);
+        if (s2 != RWPT_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return s2;
+        }
+        HIPCHK(c, ec);
+        hipError_t ei = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(c, ei);
+      }
+      HIPCHK(c, hipGraphLaunch(gx, c->stream));
+    } else {
+      st = enqueue_step(c, sort, walk);
+      if (st != RWPT_OK) return st;
+    }
+    c->sorted_valid = true;
+    c->steps += 1;
+  }
+  return RWPT_OK;
+}
+
+rwpt_status rwpt_sync(rwpt_ctx* c) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  if (!c->device_ready) return RWPT_OK;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RWPT_OK;
+}
+
+static rwpt_status fetch_sorted(rwpt_ctx* c, const DevBuf& buf, int comps, double* out, bool species_major) {
+  const int64_t N = c->N;
+  if (N == 0) return RWPT_OK;
+  const size_t ts = c->tsize, cap = (size_t)c->cap;
+  std::vector<unsigned char> h(comps * cap * ts);
+  std::vector<uint32_t> hid(N);
+  HIPCHK(c, hipMemcpyAsync(h.data(), buf.p, h.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(hid.data(), c->id.p, N * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int64_t p = 0; p < N; ++p) {
+    const uint32_t o = hid[p];
+    if ((int64_t)o >= N) return fail(c, RWPT_EDEVICE, "corrupt id map");
+    for (int k = 0; k < comps; ++k) {
+      const double v = ts == 8 ? ((const double*)h.data())[k * cap + p] : (double)((const float*)h.data())[k * cap + p];
+      if (species_major) out[(size_t)k * N + o] = v;
+      else out[(size_t)o * comps + k] = v;
+    }
+  }
+  return RWPT_OK;
+}
+
+rwpt_status rwpt_query_masses(rwpt_ctx* c, double* out) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  c->err.clear();
+  if (!c->initialized) return fail(c, RWPT_ESTATE, "query before rwpt_init_ensemble");
+  if (!out && c->N > 0) return fail(c, RWPT_EINVAL, "out is NULL");
+  return fetch_sorted(c, c->mass0, c->S, out, true);
+}
+
+rwpt_status rwpt_query_positions(rwpt_ctx* c, double* out) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  c->err.clear();
+  if (!c->initialized) return fail(c, RWPT_ESTATE, "query before rwpt_init_ensemble");
+  if (!out && c->N > 0) return fail(c, RWPT_EINVAL, "out is NULL");
+  return fetch_sorted(c, c->pos0, c->dim, out, false);
+}
+
+rwpt_status rwpt_audit(rwpt_ctx* c, double* out) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  c->err.clear();
+  if (!c->initialized) return fail(c, RWPT_ESTATE, "audit before rwpt_init_ensemble");
+  if (!out) return fail(c, RWPT_EINVAL, "out is NULL");
+  const size_t n = (size_t)c->n_real * (c->S + 1);
+  if (c->steps == 0 || c->N == 0) {
+    memcpy(out, c->audit_init.data(), n * sizeof(double));
+    return RWPT_OK;
+  }
+  HIPCHK(c, hipMemcpyAsync(out, c->audit_out.p, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RWPT_OK;
+}
+
+rwpt_status rwpt_steps_taken(rwpt_ctx* c, int64_t* out) {
+  if (!c || !out) return fail(c, RWPT_EINVAL, "NULL argument");
+  *out = c->steps;
+  return RWPT_OK;
+}
+
+rwpt_status rwpt_count_pairs(rwpt_ctx* c, double dt, double D, int64_t* pairs_out, int64_t* evals_out) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  c->err.clear();
+  if (!pairs_out) return fail(c, RWPT_EINVAL, "pairs_out is NULL");
+  if (!std::isfinite(dt) || dt <= 0.0 || !std::isfinite(D) || D < 0.0)
+    return fail(c, RWPT_EINVAL, "dt must be > 0 and D >= 0");
+  if (!c->initialized) return fail(c, RWPT_ESTATE, "count before rwpt_init_ensemble");
+  *pairs_out = 0;
+  if (evals_out) *evals_out = 0;
+  if (c->N == 0) return RWPT_OK;
+  rwpt_status st = build_grid(c, dt, D);
+  if (st != RWPT_OK) return st;
+  st = ensure_sorted(c);
+  if (st != RWPT_OK) return st;
+  PairArgs a = pair_args(c);
+  {
+    PhaseScope ps(c, PH_COUNT);
+    HIPCHK(c, launch_count(c->cfg.precision == RWPT_FP64, c->dim, c->log2l, a, c->stream));
+  }
+  std::vector<unsigned long long> h((size_t)c->ntiles * 2);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->counts.p, h.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  unsigned long long p = 0, e = 0;
+  for (int32_t t = 0; t < c->ntiles; ++t) {
+    p += h[2 * t];
+    e += h[2 * t + 1];
+  }
+  *pairs_out = (int64_t)p;
+  if (evals_out) *evals_out = (int64_t)e;
+  return RWPT_OK;
+}
+
+rwpt_status rwpt_neighbors(rwpt_ctx* c, double dt, double D, int64_t* rowptr, int32_t* cols, int64_t* nnz_out) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  c->err.clear();
+  if (!nnz_out) return fail(c, RWPT_EINVAL, "nnz_out is NULL");
+  if (!std::isfinite(dt) || dt <= 0.0 || !std::isfinite(D) || D < 0.0)
+    return fail(c, RWPT_EINVAL, "dt must be > 0 and D >= 0");
+  if (!c->initialized) return fail(c, RWPT_ESTATE, "neighbors before rwpt_init_ensemble");
+  const int64_t N = c->N;
+  if (N == 0) {
+    *nnz_out = 0;
+    if (rowptr) rowptr[0] = 0;
+    return RWPT_OK;
+  }
+  rwpt_status st = build_grid(c, dt, D);
+  if (st != RWPT_OK) return st;
+  st = ensure_sorted(c);
+  if (st != RWPT_OK) return st;
+  const int fp64 = c->cfg.precision == RWPT_FP64;
+  DevBuf cursor, rp, pairs;
+  HIPCHK(c, cursor.ensure((size_t)c->cap * 4));
+  HIPCHK(c, hipMemsetAsync(cursor.p, 0, (size_t)c->cap * 4, c->stream));
+  PairArgs a = pair_args(c);
+  a.nbr_cursor = cursor.as<uint32_t>();
+  rwpt_status result = RWPT_OK;
+  do {
+    hipError_t e = launch_nbr_count(fp64, c->dim, c->log2l, a, c->stream);
+    if (e != hipSuccess) { result = fail(c, RWPT_EDEVICE, "nbr count: %s", hipGetErrorString(e)); break; }
+    std::vector<uint32_t> cnt(N);
+    e = hipMemcpyAsync(cnt.data(), cursor.p, N * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { result = fail(c, RWPT_EDEVICE, "nbr copy: %s", hipGetErrorString(e)); break; }
+    std::vector<unsigned long long> off(N + 1, 0);
+    for (int64_t i = 0; i < N; ++i) off[i + 1] = off[i] + cnt[i];
+    const int64_t nnz = (int64_t)off[N];
+    *nnz_out = nnz;
+    if (!cols || !rowptr) break;
+    if (hipMemsetAsync(cursor.p, 0, (size_t)c->cap * 4, c->stream) != hipSuccess ||
+        rp.ensure((N + 1) * 8) != hipSuccess || pairs.ensure((size_t)std::max<int64_t>(1, nnz) * 8) != hipSuccess) {
+      result = fail(c, RWPT_ENOMEM, "neighbour export buffers");
+      break;
+    }
+    e = hipMemcpyAsync(rp.p, off.data(), (N + 1) * 8, hipMemcpyHostToDevice, c->stream);
+    a.nbr_rowptr = rp.as<unsigned long long>();
+    a.nbr_pairs = pairs.as<uint32_t>();
+    if (e == hipSuccess) e = launch_nbr_fill(fp64, c->dim, c->log2l, a, c->stream);
+    std::vector<uint32_t> hp((size_t)nnz * 2);
+    std::vector<uint32_t> hid(N);
+    if (e == hipSuccess && nnz) e = hipMemcpyAsync(hp.data(), pairs.p, (size_t)nnz * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hid.data(), c->id.p, N * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { result = fail(c, RWPT_EDEVICE, "nbr fill: %s", hipGetErrorString(e)); break; }
+    // convert to the caller's order: rows by original id, ascending columns
+    std::vector<int64_t> rc(N + 1, 0);
+    for (int64_t p = 0; p < N; ++p) rc[hid[p] + 1] = cnt[p];
+    for (int64_t i = 0; i < N; ++i) rc[i + 1] += rc[i];
+    for (int64_t i = 0; i <= N; ++i) rowptr[i] = rc[i];
+    std::vector<int64_t> fillpos(rc.begin(), rc.end() - 1);
+    for (int64_t t = 0; t < nnz; ++t) {
+      const uint32_t oi = hid[hp[2 * t]], oj = hid[hp[2 * t + 1]];
+      cols[fillpos[oi]++] = (int32_t)oj;
+    }
+    for (int64_t i = 0; i < N; ++i) std::sort(cols + rc[i], cols + rc[i + 1]);
+  } while (0);
+  cursor.release();
+  rp.release();
+  pairs.release();
+  return result;
+}
+
+rwpt_status rwpt_profile_enable(rwpt_ctx* c, int32_t on) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  if (!on && c->prof) drain_profile(c);
+  c->prof = on != 0;
+  return RWPT_OK;
+}
+
+rwpt_status rwpt_profile_reset(rwpt_ctx* c) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  drain_profile(c);
+  for (int p = 0; p < PH_N; ++p) {
+    c->prof_ms[p] = 0.0;
+    c->prof_cnt[p] = 0;
+  }
+  return RWPT_OK;
+}
+
+rwpt_status rwpt_profile_read(rwpt_ctx* c, double* ms, int64_t* cnt, int32_t* n_phases) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  drain_profile(c);
+  if (n_phases) *n_phases = PH_N;
+  for (int p = 0; p < PH_N; ++p) {
+    if (ms) ms[p] = c->prof_ms[p];
+    if (cnt) cnt[p] = c->prof_cnt[p];
+  }
+  return RWPT_OK;
+}
+
+const char* rwpt_profile_phase_name(int32_t phase) {
+  if (phase < 0 || phase >= PH_N) return "";
+  return kPhaseNames[phase];
+}
+
+rwpt_status rwpt_get_tiling(rwpt_ctx* c, int32_t* tile_lanes, double* cell_refine3) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  int lanes = c->cfg.tile_lanes ? c->cfg.tile_lanes : 8;
+  double defr[3];
+  default_refine(c->dim, defr);
+  if (tile_lanes) *tile_lanes = lanes;
+  if (cell_refine3)
+    for (int k = 0; k < 3; ++k) cell_refine3[k] = c->cfg.cell_refine[k] > 0 ? c->cfg.cell_refine[k] : defr[k];
+  return RWPT_OK;
+}
+
+rwpt_status rwpt_autotune(rwpt_ctx* c, double dt, double D, int32_t trial_steps) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  (void)dt;
+  (void)D;
+  (void)trial_steps;
+  return fail(c, RWPT_EUNSUPPORTED, "autotuning is not available in this build");
+}
+
+const char* rwpt_last_error(const rwpt_ctx* c) {
+  if (!c) return g_err.c_str();
+  return c->err.c_str();
+}
+
+void rwpt_destroy(rwpt_ctx* c) {
+  if (!c) return;
+  if (c->device_ready) {
+    (void)hipSetDevice(c->cfg.device);
+    (void)hipStreamSynchronize(c->stream);
+    drain_profile(c);
+    invalidate_graphs(c);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    DevBuf* bufs[] = {&c->pos0, &c->pos1, &c->mass0, &c->mass1, &c->id, &c->key, &c->slot,
+                      &c->tmp_src, &c->tmp_id, &c->tmp_key, &c->skey, &c->r, &c->q, &c->cell_count,
+                      &c->cell_start, &c->scan_part, &c->d_rp, &c->d_st, &c->d_tiles,
+                      &c->d_tile_start, &c->d_real_start, &c->audit_part, &c->audit_out,
+                      &c->step_ctr, &c->counts};
+    for (DevBuf* b : bufs) b->release();
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  }
+  delete c;
+}
+
+}  // extern "C"

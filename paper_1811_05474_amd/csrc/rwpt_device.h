@@ -1,0 +1,65 @@
+// rwpt_device.h -- structures shared by the host code and the HIP kernels of
+// the mass-transfer library (never by the CPU oracle).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rwpt {
+
+// Cell grid and physical parameters of one realisation, for one (dt, D).
+struct RealParams {
+  double lo[3];        // reflecting-box lower corner
+  double hi[3];        // reflecting-box upper corner
+  double inv_h[3];     // 1 / cell size per axis
+  int32_t nc[3];       // cells per axis (unused axes: 1)
+  int32_t n_stencil;   // number of neighbour-row offsets
+  int32_t stencil_off; // first entry in the stencil table
+  int32_t active;      // 1 if D_r > 0 (transfer on)
+  int64_t cell_off;    // first global cell index of this realisation
+  int64_t p_begin;     // first particle (sorted order keeps realisations contiguous)
+  int64_t p_end;
+  double rc2_d;        // cutoff^2 = (kappa*kappa) * ((8*D_r)*dt), binary64
+  double escale_d;     // -1 / sigma^2, sigma^2 = 8 D_r dt
+  float rc2_f;         // rc2_d rounded once to binary32
+  float escale_f;      // -log2(e) / sigma^2 rounded to binary32 (for exp2)
+  double amp;          // random-walk amplitude sqrt(2 D_rw dt)
+};
+
+// Offset (dy, dz) of a neighbour row of cells and how many cells (rx) to
+// extend the x-range of the tile on that row.
+struct StencilRow {
+  int32_t dy, dz, rx, pad;
+};
+
+// A run of consecutive particles (in cell-sorted order) handled by one wave.
+struct Tile {
+  int32_t begin, end, real, pad;
+};
+
+// Arguments of the pair kernels.  Floating-point arrays are binary32 or
+// binary64 according to the kernel instantiation.
+struct PairArgs {
+  const void* pos;         // [dim][cap], cell-sorted
+  int64_t cap;             // leading dimension of the position / mass arrays
+  const void* mass_in;     // [S][cap]
+  void* mass_out;          // [S][cap]
+  const void* q_in;        // 1 / r_i for the symmetric normalisation, [cap]
+  void* q_out;             // written by the row-sum pass
+  double* r_out;           // r_i = sum_j w_ij, written by the row-sum pass
+  const uint32_t* skey;    // global cell key of each sorted particle
+  const uint32_t* cell_start;
+  const Tile* tiles;
+  int32_t ntiles;
+  const RealParams* rp;
+  const StencilRow* st;
+  int32_t S;
+  int32_t react_a, react_b;
+  int32_t norm;            // 0 = symmetric, 1 = row
+  double* audit_part;      // [ntiles][S + 1]
+  unsigned long long* counts;  // count mode: [ntiles][2] (pairs j != i, evaluations)
+  uint32_t* nbr_cursor;    // neighbour export: per-particle counts / write cursors
+  const unsigned long long* nbr_rowptr;  // neighbour export: exclusive offsets
+  uint32_t* nbr_pairs;     // neighbour export: (i, j) sorted-slot pairs
+};
+
+}  // namespace rwpt

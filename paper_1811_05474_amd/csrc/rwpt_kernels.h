@@ -1,0 +1,64 @@
+// rwpt_kernels.h -- host-callable launchers of the HIP kernels (internal).
+#pragma once
+#include "rwpt_device.h"
+
+namespace rwpt {
+
+// Phase identifiers used for per-phase timing.
+enum Phase {
+  PH_WALK_KEY = 0,
+  PH_SCAN,
+  PH_SCATTER,
+  PH_CANON,
+  PH_ROWSUM,
+  PH_EXCHANGE,
+  PH_AUDIT,
+  PH_DENSE,
+  PH_COUNT,
+  PH_N
+};
+
+constexpr int kBlock = 256;        // threads per block of every kernel
+constexpr int kScanItems = 16;     // counts per thread in the cell-count scan
+constexpr int kScanChunk = kBlock * kScanItems;
+
+// Random walk + reflection (optional) and cell key / in-cell slot of every particle.
+// pos_in/pos_out may not alias.
+hipError_t launch_walk_key(int fp64, int dim, const void* pos_in, void* pos_out, int64_t cap,
+                           const uint32_t* id, int32_t n, const RealParams* rp,
+                           const int64_t* real_start, int32_t n_real, const uint64_t* step_ctr,
+                           uint64_t seed, int32_t do_walk, uint32_t* cell_count, uint32_t* key,
+                           uint32_t* slot, hipStream_t s);
+
+// Exclusive scan of cell_count[0..ncell) into cell_start[0..ncell]; zeroes cell_count.
+// partials must hold ceil(ncell / kScanChunk) + 1 entries.
+hipError_t launch_cell_scan(uint32_t* cell_count, uint32_t* cell_start, int64_t ncell,
+                            uint32_t* partials, hipStream_t s);
+
+// Place every particle at cell_start[key] + slot (arrival order inside a cell).
+hipError_t launch_scatter(int32_t n, const uint32_t* key, const uint32_t* slot,
+                          const uint32_t* cell_start, const uint32_t* id, uint32_t* tmp_src,
+                          uint32_t* tmp_id, uint32_t* tmp_key, hipStream_t s);
+
+// Reorder inside every cell by particle id (canonical order), gathering
+// positions, masses, ids and keys into the sorted arrays.
+hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
+                        const uint32_t* tmp_id, const uint32_t* tmp_key,
+                        const uint32_t* cell_start, const void* pos_in, void* pos_out,
+                        int64_t cap, const void* mass_in, void* mass_out, int32_t S,
+                        uint32_t* id_out, uint32_t* skey, hipStream_t s);
+
+// Pair kernels (one wave per tile).  log2l: lanes per particle = 1 << log2l.
+hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
+hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
+hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
+hipError_t launch_nbr_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
+hipError_t launch_nbr_fill(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
+
+// Per-realisation FP64 reduction of the per-tile audit partials; optionally
+// advances the device step counter.
+hipError_t launch_audit_reduce(const double* part, int32_t S1, const int32_t* tile_start,
+                               int32_t n_real, double* out, uint64_t* step_ctr, int32_t bump,
+                               hipStream_t s);
+
+}  // namespace rwpt

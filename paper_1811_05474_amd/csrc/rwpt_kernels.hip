@@ -1,0 +1,843 @@
+// rwpt_kernels.hip -- HIP kernels (gfx950) of one explicit step of the
+// particle mass-transfer method of arXiv:1811.05474:
+//   walk + cell key  -> counting sort into a uniform cell grid (cell-count scan,
+//   scatter, canonical in-cell order) -> row sums r_i -> weights + exchange +
+//   reaction + audit partials -> per-realisation audit.
+//
+// Layout: structure-of-arrays, positions pos[k][cap] and masses mass[s][cap],
+// kept in cell-sorted order; id[p] maps a sorted slot back to the caller's
+// particle index.  Every reduction runs in a fixed order, so results are
+// bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <type_traits>
+
+#include "rwpt_kernels.h"
+
+namespace rwpt {
+
+// ---------------------------------------------------------------------------
+// Small device helpers
+// ---------------------------------------------------------------------------
+
+// Wave-uniform block index -> logical block so that each of the 8 XCDs (which
+// receive workgroups round-robin) works on one contiguous range of tiles and
+// neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int per = nb >> 3, rem = nb & 7;
+  const int x = b & 7, q = b >> 3;
+  return x * per + (x < rem ? x : rem) + q;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): 10 rounds of the
+// multiply/xor S-box with the key bumped by the golden-ratio and sqrt(3)-1
+// Weyl constants between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t a0 = c[0], a2 = c[2];
+    const uint32_t hi0 = __umulhi(0xD2511F53u, a0), lo0 = 0xD2511F53u * a0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, a2), lo1 = 0xCD9E8D57u * a2;
+    c[0] = hi1 ^ c[1] ^ k0;
+    c[1] = lo1;
+    c[2] = hi0 ^ c[3] ^ k1;
+    c[3] = lo0;
+  }
+}
+
+__device__ __forceinline__ void sincospi_t(float x, float* s, float* c) { sincospif(x, s, c); }
+__device__ __forceinline__ void sincospi_t(double x, double* s, double* c) { sincospi(x, s, c); }
+
+// Three standard normals for (particle id, step) under the 64-bit seed:
+// counter (id, step lo, step hi, 0); uniforms u = w * 2^-32 + 2^-33;
+// Box-Muller on (u0, u1) and (u2, u3).
+template <typename T, int DIM>
+__device__ __forceinline__ void walk_normals(uint32_t pid, uint64_t seed, uint64_t step, T z[3]) {
+  uint32_t c[4] = {pid, (uint32_t)step, (uint32_t)(step >> 32), 0u};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const T s32 = (T)2.3283064365386962890625e-10;   // 2^-32
+  const T half = (T)1.16415321826934814453125e-10; // 2^-33
+  const T u0 = (T)c[0] * s32 + half;
+  const T u1 = (T)c[1] * s32 + half;
+  const T ra = sqrt((T)-2 * log(u0));
+  T sn, cs;
+  sincospi_t((T)2 * u1, &sn, &cs);
+  z[0] = ra * cs;
+  z[1] = ra * sn;
+  z[2] = (T)0;
+  if constexpr (DIM > 2) {
+    const T u2 = (T)c[2] * s32 + half;
+    const T u3 = (T)c[3] * s32 + half;
+    const T rb = sqrt((T)-2 * log(u2));
+    T sn2, cs2;
+    sincospi_t((T)2 * u3, &sn2, &cs2);
+    z[2] = rb * cs2;
+  }
+}
+
+// Mirror at zero-flux walls until inside the closed box.
+template <typename T>
+__device__ __forceinline__ T reflect(T x, T lo, T hi) {
+  for (int it = 0; it < 64 && (x < lo || x > hi); ++it) x = (x < lo) ? (T)2 * lo - x : (T)2 * hi - x;
+  x = x < lo ? lo : x;
+  x = x > hi ? hi : x;
+  return x;
+}
+
+// Squared separation used by the cutoff predicate: ((dx*dx) + (dy*dy)) + (dz*dz)
+// in the path's precision, every operation rounded (no contraction), so the
+// neighbour sets are reproducible bit for bit.
+template <typename T, int DIM>
+__device__ __forceinline__ T sep2(const T xi[DIM], const T* __restrict__ pos, int64_t cap, uint32_t j) {
+#pragma clang fp contract(off)
+  const T d0 = pos[j] - xi[0];
+  T s = d0 * d0;
+  if constexpr (DIM > 1) {
+    const T d1 = pos[cap + j] - xi[1];
+    s = s + d1 * d1;
+  }
+  if constexpr (DIM > 2) {
+    const T d2 = pos[2 * cap + j] - xi[2];
+    s = s + d2 * d2;
+  }
+  return s;
+}
+
+// Co-location weight exp(-s2 / sigma^2) (Eq. 3 without prefactor): binary32
+// uses the hardware exp2 with the scale -log2(e)/sigma^2; binary64 uses the
+// library exp.
+__device__ __forceinline__ float kweight(float s2, float escale) {
+  return __builtin_amdgcn_exp2f(s2 * escale);
+}
+__device__ __forceinline__ double kweight(double s2, double escale) { return exp(s2 * escale); }
+
+template <typename T>
+__device__ __forceinline__ T rc2_of(const RealParams& P);
+template <>
+__device__ __forceinline__ float rc2_of<float>(const RealParams& P) { return P.rc2_f; }
+template <>
+__device__ __forceinline__ double rc2_of<double>(const RealParams& P) { return P.rc2_d; }
+template <typename T>
+__device__ __forceinline__ T escale_of(const RealParams& P);
+template <>
+__device__ __forceinline__ float escale_of<float>(const RealParams& P) { return P.escale_f; }
+template <>
+__device__ __forceinline__ double escale_of<double>(const RealParams& P) { return P.escale_d; }
+
+// ---------------------------------------------------------------------------
+// Walk + key
+// ---------------------------------------------------------------------------
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_walk_key(
+    const T* __restrict__ pos_in, T* __restrict__ pos_out, int64_t cap,
+    const uint32_t* __restrict__ id, int32_t n, const RealParams* __restrict__ rp,
+    const int64_t* __restrict__ real_start, int32_t n_real, const uint64_t* __restrict__ step_ctr,
+    uint64_t seed, int32_t do_walk, uint32_t* __restrict__ cell_count, uint32_t* __restrict__ key_out,
+    uint32_t* __restrict__ slot_out) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n) return;
+  int lo = 0, hi = n_real - 1;  // last realisation whose first particle is <= p
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (real_start[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  const RealParams& P = rp[lo];
+  T x[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) x[k] = pos_in[k * cap + p];
+  if (do_walk && P.amp > 0.0) {
+    T z[3];
+    walk_normals<T, DIM>(id[p], seed, *step_ctr, z);
+    const T amp = (T)P.amp;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) x[k] = reflect<T>(x[k] + amp * z[k], (T)P.lo[k], (T)P.hi[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) pos_out[k * cap + p] = x[k];
+  int64_t c = 0;
+#pragma unroll
+  for (int k = DIM - 1; k >= 0; --k) {
+    const double u = ((double)x[k] - P.lo[k]) * P.inv_h[k];
+    int ck = (int)floor(u);
+    ck = ck < 0 ? 0 : ck;
+    ck = ck > P.nc[k] - 1 ? P.nc[k] - 1 : ck;
+    c = c * P.nc[k] + ck;
+  }
+  const uint32_t key = (uint32_t)(P.cell_off + c);
+  key_out[p] = key;
+  slot_out[p] = atomicAdd(&cell_count[key], 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of the cell counts
+// ---------------------------------------------------------------------------
+
+// Inclusive scan across the 256 threads of a block; returns the inclusive
+// value and the block total.
+__device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(v, off);
+    if (lane >= off) v += t;
+  }
+  if (lane == 63) sh[wave] = v;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int w = 0; w < wave; ++w) base += sh[w];
+  *total = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return v + base;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ cnt, int64_t n,
+                                                        uint32_t* __restrict__ partials) {
+  __shared__ uint32_t sh[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) s += cnt[base + i];
+  uint32_t total;
+  block_inclusive_scan(s, sh, &total);
+  if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+// Single block: exclusive scan of the block partials in place; writes the
+// grand total to *grand.
+__global__ __launch_bounds__(kBlock) void k_scan_top(uint32_t* __restrict__ partials, int32_t nb,
+                                                     uint32_t* __restrict__ grand) {
+  __shared__ uint32_t sh[4];
+  const int per = (nb + kBlock - 1) / kBlock;
+  const int b0 = threadIdx.x * per;
+  uint32_t s = 0;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) s += partials[b0 + i];
+  uint32_t total;
+  const uint32_t incl = block_inclusive_scan(s, sh, &total);
+  uint32_t run = incl - s;
+  for (int i = 0; i < per; ++i)
+    if (b0 + i < nb) {
+      const uint32_t v = partials[b0 + i];
+      partials[b0 + i] = run;
+      run += v;
+    }
+  if (threadIdx.x == 0) *grand = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t* __restrict__ cnt, int64_t n,
+                                                       const uint32_t* __restrict__ partials,
+                                                       uint32_t* __restrict__ start) {
+  __shared__ uint32_t sh[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? cnt[base + i] : 0u;
+    s += v[i];
+  }
+  uint32_t total;
+  const uint32_t incl = block_inclusive_scan(s, sh, &total);
+  uint32_t run = partials[blockIdx.x] + incl - s;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) {
+      start[base + i] = run;
+      run += v[i];
+      cnt[base + i] = 0u;  // ready for the next step's counting
+    }
+}
+
+__global__ void k_scan_tail(uint32_t* __restrict__ start, int64_t n, const uint32_t* __restrict__ grand) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) start[n] = *grand;
+}
+
+// ---------------------------------------------------------------------------
+// Scatter and canonical in-cell order
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_scatter(int32_t n, const uint32_t* __restrict__ key,
+                                                    const uint32_t* __restrict__ slot,
+                                                    const uint32_t* __restrict__ cell_start,
+                                                    const uint32_t* __restrict__ id,
+                                                    uint32_t* __restrict__ tmp_src,
+                                                    uint32_t* __restrict__ tmp_id,
+                                                    uint32_t* __restrict__ tmp_key) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t k = key[p];
+  const uint32_t dst = cell_start[k] + slot[p];
+  tmp_src[dst] = (uint32_t)p;
+  tmp_id[dst] = id[p];
+  tmp_key[dst] = k;
+}
+
+// The atomic slot of the scatter depends on arrival order; ranking by the
+// (unique) particle id inside each cell makes the sorted order a function of
+// the positions alone: (cell, id).
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_canon(
+    int32_t n, const uint32_t* __restrict__ tmp_src, const uint32_t* __restrict__ tmp_id,
+    const uint32_t* __restrict__ tmp_key, const uint32_t* __restrict__ cell_start,
+    const T* __restrict__ pos_in, T* __restrict__ pos_out, int64_t cap, const T* __restrict__ mass_in,
+    T* __restrict__ mass_out, int32_t S, uint32_t* __restrict__ id_out, uint32_t* __restrict__ skey) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n) return;
+  const uint32_t k = tmp_key[e];
+  const uint32_t cs = cell_start[k], ce = cell_start[k + 1];
+  const uint32_t my = tmp_id[e];
+  uint32_t rank = 0;
+  for (uint32_t f = cs; f < ce; ++f) rank += (tmp_id[f] < my) ? 1u : 0u;
+  const uint32_t dst = cs + rank;
+  const uint32_t src = tmp_src[e];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) pos_out[d * cap + dst] = pos_in[d * cap + src];
+  for (int s = 0; s < S; ++s) mass_out[s * cap + dst] = mass_in[s * cap + src];
+  id_out[dst] = my;
+  skey[dst] = k;
+}
+
+// ---------------------------------------------------------------------------
+// Pair kernels
+//
+// One wave handles a tile of G = 64 / L consecutive sorted particles; lane
+// = gl * G + gi pairs particle gi of the tile with every L-th candidate
+// (offset gl).  The tile is split into segments of one cell row each; for a
+// segment the candidates are, on every neighbour row of the stencil, the
+// contiguous sorted range of cells [cx_first - rx, cx_last + rx].  Every
+// candidate is still decided by the exact cutoff predicate.
+// ---------------------------------------------------------------------------
+
+struct TileLane {
+  int gi, gl, n_in, row, cx;
+  bool valid;
+  int32_t i;
+};
+
+template <int LOG2L, typename RowFn>
+__device__ __forceinline__ void for_tile_rows(const RealParams& P, const StencilRow* __restrict__ st,
+                                              const uint32_t* __restrict__ cell_start,
+                                              const TileLane& tl, RowFn&& fn) {
+  const int nc0 = P.nc[0], nc1 = P.nc[1], nc2 = P.nc[2];
+  int seg = 0;
+  while (seg < tl.n_in) {
+    const int seg_row = __builtin_amdgcn_readlane(tl.row, seg);
+    const unsigned long long m =
+        __ballot(tl.gl == 0 && tl.gi > seg && (tl.gi >= tl.n_in || tl.row != seg_row));
+    int seg_end = m ? (__ffsll((unsigned long long)m) - 1) : tl.n_in;
+    seg_end = seg_end > tl.n_in ? tl.n_in : seg_end;
+    const int cxa = __builtin_amdgcn_readlane(tl.cx, seg);
+    const int cxb = __builtin_amdgcn_readlane(tl.cx, seg_end - 1);
+    const bool act = tl.valid && tl.gi >= seg && tl.gi < seg_end;
+    const int cy = seg_row % nc1, cz = seg_row / nc1;
+    for (int r = 0; r < P.n_stencil; ++r) {
+      const StencilRow sr = st[P.stencil_off + r];
+      const int ny = cy + sr.dy, nz = cz + sr.dz;
+      if (ny < 0 || ny >= nc1 || nz < 0 || nz >= nc2) continue;
+      const int xa = cxa - sr.rx < 0 ? 0 : cxa - sr.rx;
+      const int xb = cxb + sr.rx > nc0 - 1 ? nc0 - 1 : cxb + sr.rx;
+      const int64_t cb = P.cell_off + ((int64_t)nz * nc1 + ny) * nc0;
+      const uint32_t jb = cell_start[cb + xa];
+      const uint32_t je = cell_start[cb + xb + 1];
+      fn(jb, je, act);
+    }
+    seg = seg_end;
+  }
+}
+
+// Load the tile header and this lane's particle.
+template <int LOG2L>
+__device__ __forceinline__ bool tile_lane_setup(const PairArgs& a, TileLane& tl, Tile& tile) {
+  constexpr int G = 64 >> LOG2L;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int t = blk * (kBlock / 64) + wave;
+  if (t >= a.ntiles) return false;
+  tile = a.tiles[t];
+  tl.gi = lane & (G - 1);
+  tl.gl = lane >> (6 - LOG2L);
+  tl.n_in = tile.end - tile.begin;
+  tl.i = tile.begin + tl.gi;
+  tl.valid = tl.gi < tl.n_in;
+  return true;
+}
+
+template <typename T, int DIM, int LOG2L>
+__global__ __launch_bounds__(kBlock) void k_rowsum(PairArgs a) {
+  constexpr int L = 1 << LOG2L;
+  constexpr int G = 64 >> LOG2L;
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<LOG2L>(a, tl, tile)) return;
+  const RealParams& P = a.rp[tile.real];
+  const T* __restrict__ pos = (const T*)a.pos;
+  const int64_t cap = a.cap;
+  const int32_t ii = tl.valid ? tl.i : tile.end - 1;
+  T xi[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  const uint32_t lk = a.skey[ii] - (uint32_t)P.cell_off;
+  tl.cx = (int)(lk % (uint32_t)P.nc[0]);
+  tl.row = (int)(lk / (uint32_t)P.nc[0]);
+  const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
+  double acc = 0.0;
+  if (P.active) {
+    for_tile_rows<LOG2L>(P, a.st, a.cell_start, tl, [&](uint32_t jb, uint32_t je, bool act) {
+      T accr = (T)0;
+      const uint32_t len = je - jb, nfull = len >> LOG2L, rem = len & (L - 1);
+      uint32_t j = jb + tl.gl;
+      for (uint32_t c = 0; c < nfull; ++c, j += L) {
+        const T s2 = sep2<T, DIM>(xi, pos, cap, j);
+        const T w = kweight(s2, esc);
+        accr += (act && s2 <= rc2) ? w : (T)0;
+      }
+      if (rem && (uint32_t)tl.gl < rem) {
+        const T s2 = sep2<T, DIM>(xi, pos, cap, j);
+        const T w = kweight(s2, esc);
+        accr += (act && s2 <= rc2) ? w : (T)0;
+      }
+      acc += (double)accr;
+    });
+  } else {
+    acc = 1.0;  // only the self weight
+  }
+#pragma unroll
+  for (int off = G; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
+  if (tl.gl == 0 && tl.valid) {
+    if (!P.active) acc = 1.0;
+    a.r_out[tl.i] = acc;
+    ((T*)a.q_out)[tl.i] = (T)(1.0 / acc);
+  }
+}
+
+template <typename T, int DIM, int SMAX, int LOG2L>
+__global__ __launch_bounds__(kBlock) void k_exchange(PairArgs a) {
+  constexpr int L = 1 << LOG2L;
+  constexpr int G = 64 >> LOG2L;
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<LOG2L>(a, tl, tile)) return;
+  const RealParams& P = a.rp[tile.real];
+  const T* __restrict__ pos = (const T*)a.pos;
+  const T* __restrict__ min_ = (const T*)a.mass_in;
+  const T* __restrict__ q = (const T*)a.q_in;
+  const int64_t cap = a.cap;
+  const int S = a.S;
+  const int32_t ii = tl.valid ? tl.i : tile.end - 1;
+  T xi[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  T Mi[SMAX];
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) Mi[s] = (s < S) ? min_[s * cap + ii] : (T)0;
+  const uint32_t lk = a.skey[ii] - (uint32_t)P.cell_off;
+  tl.cx = (int)(lk % (uint32_t)P.nc[0]);
+  tl.row = (int)(lk / (uint32_t)P.nc[0]);
+  const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
+  double acc[SMAX];
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) acc[s] = 0.0;
+  double racc = 0.0;
+  const bool sym = (a.norm == 0);
+  if (P.active) {
+    if (sym) {
+      const T qi = q[ii];
+      for_tile_rows<LOG2L>(P, a.st, a.cell_start, tl, [&](uint32_t jb, uint32_t je, bool act) {
+        T accr[SMAX];
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) accr[s] = (T)0;
+        const uint32_t len = je - jb, nfull = len >> LOG2L, rem = len & (L - 1);
+        uint32_t j = jb + tl.gl;
+        auto body = [&](uint32_t jj) {
+          const T s2 = sep2<T, DIM>(xi, pos, cap, jj);
+          T w = kweight(s2, esc);
+          w = (act && s2 <= rc2) ? w : (T)0;
+          const T p = w * (qi + q[jj]);  // 2 * symmetric P_ij
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s)
+            if (s < S) accr[s] += p * (min_[s * cap + jj] - Mi[s]);
+        };
+        for (uint32_t c = 0; c < nfull; ++c, j += L) body(j);
+        if (rem && (uint32_t)tl.gl < rem) body(j);
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
+      });
+    } else {
+      for_tile_rows<LOG2L>(P, a.st, a.cell_start, tl, [&](uint32_t jb, uint32_t je, bool act) {
+        T accr[SMAX];
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) accr[s] = (T)0;
+        T rr = (T)0;
+        const uint32_t len = je - jb, nfull = len >> LOG2L, rem = len & (L - 1);
+        uint32_t j = jb + tl.gl;
+        auto body = [&](uint32_t jj) {
+          const T s2 = sep2<T, DIM>(xi, pos, cap, jj);
+          T w = kweight(s2, esc);
+          w = (act && s2 <= rc2) ? w : (T)0;
+          rr += w;
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s)
+            if (s < S) accr[s] += w * (min_[s * cap + jj] - Mi[s]);
+        };
+        for (uint32_t c = 0; c < nfull; ++c, j += L) body(j);
+        if (rem && (uint32_t)tl.gl < rem) body(j);
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
+        racc += (double)rr;
+      });
+    }
+  }
+#pragma unroll
+  for (int off = G; off < 64; off <<= 1) {
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) acc[s] += __shfl_xor(acc[s], off);
+    racc += __shfl_xor(racc, off);
+  }
+  // New masses (Eq. 6), reaction, audit contributions.
+  double tot[SMAX + 1];
+#pragma unroll
+  for (int s = 0; s <= SMAX; ++s) tot[s] = 0.0;
+  if (tl.gl == 0 && tl.valid) {
+    double Mn[SMAX];
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      double dm = 0.0;
+      if (P.active) dm = sym ? 0.25 * acc[s] : 0.5 * acc[s] / racc;
+      Mn[s] = (double)Mi[s] + dm;
+    }
+    if (a.react_a >= 0) {
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s)
+        if (s == a.react_a) {
+#pragma unroll
+          for (int t2 = 0; t2 < SMAX; ++t2)
+            if (t2 == a.react_b) {
+              double m = Mn[s] < Mn[t2] ? Mn[s] : Mn[t2];
+              m = m > 0.0 ? m : 0.0;
+              Mn[s] -= m;
+              Mn[t2] -= m;
+            }
+        }
+    }
+    T* __restrict__ mout = (T*)a.mass_out;
+    double va = 0.0, vb = 0.0;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s)
+      if (s < S) {
+        const T v = (T)Mn[s];
+        mout[s * cap + tl.i] = v;
+        tot[s] = (double)v;
+        if (s == a.react_a) va = (double)v;
+        if (s == a.react_b) vb = (double)v;
+      }
+    tot[SMAX] = va - vb;
+  }
+  // audit partials of this tile: lanes 0..G-1 hold the values
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+#pragma unroll
+    for (int s = 0; s <= SMAX; ++s) tot[s] += __shfl_xor(tot[s], off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    const int t = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    double* part = a.audit_part + (int64_t)t * (S + 1);
+    for (int s = 0; s < S; ++s) part[s] = tot[s < SMAX ? s : 0];
+    part[S] = tot[SMAX];
+  }
+}
+
+// Counts ordered pairs j != i within the cutoff and candidate evaluations.
+template <typename T, int DIM, int LOG2L>
+__global__ __launch_bounds__(kBlock) void k_count(PairArgs a) {
+  constexpr int L = 1 << LOG2L;
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<LOG2L>(a, tl, tile)) return;
+  const RealParams& P = a.rp[tile.real];
+  const T* __restrict__ pos = (const T*)a.pos;
+  const int64_t cap = a.cap;
+  const int32_t ii = tl.valid ? tl.i : tile.end - 1;
+  T xi[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  const uint32_t lk = a.skey[ii] - (uint32_t)P.cell_off;
+  tl.cx = (int)(lk % (uint32_t)P.nc[0]);
+  tl.row = (int)(lk / (uint32_t)P.nc[0]);
+  const T rc2 = rc2_of<T>(P);
+  unsigned long long pairs = 0, evals = 0;
+  if (P.active) {
+    for_tile_rows<LOG2L>(P, a.st, a.cell_start, tl, [&](uint32_t jb, uint32_t je, bool act) {
+      const uint32_t len = je - jb, nfull = len >> LOG2L, rem = len & (L - 1);
+      uint32_t j = jb + tl.gl;
+      auto body = [&](uint32_t jj) {
+        const T s2 = sep2<T, DIM>(xi, pos, cap, jj);
+        if (act) {
+          ++evals;
+          if (s2 <= rc2 && jj != (uint32_t)tl.i) ++pairs;
+        }
+      };
+      for (uint32_t c = 0; c < nfull; ++c, j += L) body(j);
+      if (rem && (uint32_t)tl.gl < rem) body(j);
+    });
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    pairs += __shfl_xor(pairs, off);
+    evals += __shfl_xor(evals, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    const int t = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    a.counts[2 * t] = pairs;
+    a.counts[2 * t + 1] = evals;
+  }
+}
+
+// Neighbour export: FILL = false counts per particle (j = i included), FILL =
+// true writes (i, j) sorted-slot pairs at rowptr[i] + cursor.
+template <typename T, int DIM, int LOG2L, bool FILL>
+__global__ __launch_bounds__(kBlock) void k_nbr(PairArgs a) {
+  constexpr int L = 1 << LOG2L;
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<LOG2L>(a, tl, tile)) return;
+  const RealParams& P = a.rp[tile.real];
+  const T* __restrict__ pos = (const T*)a.pos;
+  const int64_t cap = a.cap;
+  const int32_t ii = tl.valid ? tl.i : tile.end - 1;
+  T xi[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  const uint32_t lk = a.skey[ii] - (uint32_t)P.cell_off;
+  tl.cx = (int)(lk % (uint32_t)P.nc[0]);
+  tl.row = (int)(lk / (uint32_t)P.nc[0]);
+  const T rc2 = rc2_of<T>(P);
+  if (!P.active) {
+    if (tl.valid && tl.gl == 0) {
+      if (FILL) {
+        const uint32_t at = atomicAdd(&a.nbr_cursor[tl.i], 1u);
+        const unsigned long long o = a.nbr_rowptr[tl.i] + at;
+        a.nbr_pairs[2 * o] = (uint32_t)tl.i;
+        a.nbr_pairs[2 * o + 1] = (uint32_t)tl.i;
+      } else {
+        atomicAdd(&a.nbr_cursor[tl.i], 1u);
+      }
+    }
+    return;
+  }
+  for_tile_rows<LOG2L>(P, a.st, a.cell_start, tl, [&](uint32_t jb, uint32_t je, bool act) {
+    const uint32_t len = je - jb, nfull = len >> LOG2L, rem = len & (L - 1);
+    uint32_t j = jb + tl.gl;
+    auto body = [&](uint32_t jj) {
+      const T s2 = sep2<T, DIM>(xi, pos, cap, jj);
+      if (act && s2 <= rc2) {
+        const uint32_t at = atomicAdd(&a.nbr_cursor[tl.i], 1u);
+        if (FILL) {
+          const unsigned long long o = a.nbr_rowptr[tl.i] + at;
+          a.nbr_pairs[2 * o] = (uint32_t)tl.i;
+          a.nbr_pairs[2 * o + 1] = jj;
+        }
+      }
+    };
+    for (uint32_t c = 0; c < nfull; ++c, j += L) body(j);
+    if (rem && (uint32_t)tl.gl < rem) body(j);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Audit
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_audit_reduce(const double* __restrict__ part, int32_t S1,
+                                                         const int32_t* __restrict__ tile_start,
+                                                         int32_t n_real, double* __restrict__ out,
+                                                         uint64_t* __restrict__ step_ctr, int32_t bump) {
+  __shared__ double sh[kBlock];
+  const int r = blockIdx.x;
+  const int t0 = tile_start[r], t1 = tile_start[r + 1];
+  for (int v = 0; v < S1; ++v) {
+    double s = 0.0;
+    for (int t = t0 + threadIdx.x; t < t1; t += kBlock) s += part[(int64_t)t * S1 + v];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)r * S1 + v] = sh[0];
+    __syncthreads();
+  }
+  if (bump && r == 0 && threadIdx.x == 0) *step_ctr = *step_ctr + 1;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_walk_key(int fp64, int dim, const void* pos_in, void* pos_out, int64_t cap,
+                           const uint32_t* id, int32_t n, const RealParams* rp,
+                           const int64_t* real_start, int32_t n_real, const uint64_t* step_ctr,
+                           uint64_t seed, int32_t do_walk, uint32_t* cell_count, uint32_t* key,
+                           uint32_t* slot, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 g(blocks_for(n)), b(kBlock);
+#define RWPT_WK(T, D)                                                                             \
+  hipLaunchKernelGGL((k_walk_key<T, D>), g, b, 0, s, (const T*)pos_in, (T*)pos_out, cap, id, n, rp, \
+                     real_start, n_real, step_ctr, seed, do_walk, cell_count, key, slot)
+  if (fp64) {
+    if (dim == 1) RWPT_WK(double, 1);
+    else if (dim == 2) RWPT_WK(double, 2);
+    else RWPT_WK(double, 3);
+  } else {
+    if (dim == 1) RWPT_WK(float, 1);
+    else if (dim == 2) RWPT_WK(float, 2);
+    else RWPT_WK(float, 3);
+  }
+#undef RWPT_WK
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_scan(uint32_t* cell_count, uint32_t* cell_start, int64_t ncell,
+                            uint32_t* partials, hipStream_t s) {
+  const int64_t nb = (ncell + kScanChunk - 1) / kScanChunk;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, cell_count, ncell, partials);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, partials, (int32_t)nb, partials + nb);
+  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, cell_count, ncell, partials,
+                     cell_start);
+  hipLaunchKernelGGL(k_scan_tail, dim3(1), dim3(64), 0, s, cell_start, ncell, partials + nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(int32_t n, const uint32_t* key, const uint32_t* slot,
+                          const uint32_t* cell_start, const uint32_t* id, uint32_t* tmp_src,
+                          uint32_t* tmp_id, uint32_t* tmp_key, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, key, slot, cell_start, id,
+                     tmp_src, tmp_id, tmp_key);
+  return hipGetLastError();
+}
+
+hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
+                        const uint32_t* tmp_id, const uint32_t* tmp_key,
+                        const uint32_t* cell_start, const void* pos_in, void* pos_out,
+                        int64_t cap, const void* mass_in, void* mass_out, int32_t S,
+                        uint32_t* id_out, uint32_t* skey, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 g(blocks_for(n)), b(kBlock);
+#define RWPT_CN(T, D)                                                                           \
+  hipLaunchKernelGGL((k_canon<T, D>), g, b, 0, s, n, tmp_src, tmp_id, tmp_key, cell_start,        \
+                     (const T*)pos_in, (T*)pos_out, cap, (const T*)mass_in, (T*)mass_out, S, id_out, \
+                     skey)
+  if (fp64) {
+    if (dim == 1) RWPT_CN(double, 1);
+    else if (dim == 2) RWPT_CN(double, 2);
+    else RWPT_CN(double, 3);
+  } else {
+    if (dim == 1) RWPT_CN(float, 1);
+    else if (dim == 2) RWPT_CN(float, 2);
+    else RWPT_CN(float, 3);
+  }
+#undef RWPT_CN
+  return hipGetLastError();
+}
+
+static inline dim3 pair_grid(int32_t ntiles) {
+  return dim3((unsigned)((ntiles + (kBlock / 64) - 1) / (kBlock / 64)));
+}
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Calls f(T{}, IC<dim>{}, IC<log2l>{}) for the supported instantiations.
+template <typename F>
+static hipError_t dispatch_tdl(int fp64, int dim, int log2l, F&& f) {
+  auto with_l = [&](auto t, auto d) -> hipError_t {
+    switch (log2l) {
+      case 0: f(t, d, IC<0>{}); break;
+      case 2: f(t, d, IC<2>{}); break;
+      case 3: f(t, d, IC<3>{}); break;
+      case 4: f(t, d, IC<4>{}); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  };
+  auto with_d = [&](auto t) -> hipError_t {
+    switch (dim) {
+      case 1: return with_l(t, IC<1>{});
+      case 2: return with_l(t, IC<2>{});
+      case 3: return with_l(t, IC<3>{});
+      default: return hipErrorInvalidValue;
+    }
+  };
+  return fp64 ? with_d(double{}) : with_d(float{});
+}
+
+hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  const dim3 g = pair_grid(a.ntiles), b(kBlock);
+  return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
+    using T = decltype(t);
+    hipLaunchKernelGGL((k_rowsum<T, decltype(d)::value, decltype(l)::value>), g, b, 0, s, a);
+  });
+}
+
+hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  if (a.S < 1 || a.S > 8) return hipErrorInvalidValue;
+  const dim3 g = pair_grid(a.ntiles), b(kBlock);
+  return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
+    using T = decltype(t);
+    constexpr int D = decltype(d)::value, L = decltype(l)::value;
+    if (a.S <= 2) hipLaunchKernelGGL((k_exchange<T, D, 2, L>), g, b, 0, s, a);
+    else if (a.S <= 4) hipLaunchKernelGGL((k_exchange<T, D, 4, L>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_exchange<T, D, 8, L>), g, b, 0, s, a);
+  });
+}
+
+hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  const dim3 g = pair_grid(a.ntiles), b(kBlock);
+  return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
+    using T = decltype(t);
+    hipLaunchKernelGGL((k_count<T, decltype(d)::value, decltype(l)::value>), g, b, 0, s, a);
+  });
+}
+
+hipError_t launch_nbr_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  const dim3 g = pair_grid(a.ntiles), b(kBlock);
+  return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
+    using T = decltype(t);
+    hipLaunchKernelGGL((k_nbr<T, decltype(d)::value, decltype(l)::value, false>), g, b, 0, s, a);
+  });
+}
+
+hipError_t launch_nbr_fill(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  const dim3 g = pair_grid(a.ntiles), b(kBlock);
+  return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
+    using T = decltype(t);
+    hipLaunchKernelGGL((k_nbr<T, decltype(d)::value, decltype(l)::value, true>), g, b, 0, s, a);
+  });
+}
+
+hipError_t launch_audit_reduce(const double* part, int32_t S1, const int32_t* tile_start,
+                               int32_t n_real, double* out, uint64_t* step_ctr, int32_t bump,
+                               hipStream_t s) {
+  if (n_real <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_audit_reduce, dim3((unsigned)n_real), dim3(kBlock), 0, s, part, S1, tile_start,
+                     n_real, out, step_ctr, bump);
+  return hipGetLastError();
+}
+
+}  // namespace rwpt

@@ -1,0 +1,138 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol include/rwpt.h declares, and validates arguments before any
+device work."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1811_05474_amd import rwpt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(rwpt.LIB_PATH):
+        from paper_1811_05474_amd import _build
+        _build.build()
+    return rwpt.load_library()
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "rwpt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rwpt_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(rwpt.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert "gfx950" in rwpt.rwpt_version()
+
+
+def test_config_struct_matches_c_layout(lib):
+    cfg = rwpt.rwpt_config_default()
+    assert cfg.dim == 2 and cfg.n_species == 2 and cfg.react_a == 0 and cfg.react_b == 1
+    assert cfg.kappa == 3.0 and cfg.rw_ratio == 1.0 and cfg.use_graph == 1
+    assert list(cfg.box_hi) == [1.0, 1.0, 1.0]
+
+
+@pytest.mark.parametrize("field,value", [
+    ("dim", 0), ("dim", 4), ("n_species", 0), ("n_species", 9), ("react_a", 5), ("kappa", 0.0),
+    ("kappa", -1.0), ("kappa", float("nan")), ("rw_ratio", -1.0), ("precision", 2), ("norm", 3),
+    ("path", 7), ("tile_lanes", 3), ("tile_lanes", 32), ("device", -1), ("use_graph", 2),
+])
+def test_create_rejects_bad_config(lib, field, value):
+    cfg = rwpt.rwpt_config_default()
+    setattr(cfg, field, value)
+    with pytest.raises(rwpt.RwptError) as ei:
+        rwpt.rwpt_create(cfg)
+    assert ei.value.status == rwpt.RWPT_EINVAL
+    assert rwpt.rwpt_last_error(None)
+
+
+def test_create_rejects_bad_box_and_reaction(lib):
+    cfg = rwpt.rwpt_config_default()
+    cfg.box_lo[1] = 2.0
+    with pytest.raises(rwpt.RwptError):
+        rwpt.rwpt_create(cfg)
+    cfg = rwpt.rwpt_config_default()
+    cfg.react_a, cfg.react_b = 1, 1
+    with pytest.raises(rwpt.RwptError):
+        rwpt.rwpt_create(cfg)
+    cfg = rwpt.rwpt_config_default()
+    cfg.react_a, cfg.react_b = 0, -1
+    with pytest.raises(rwpt.RwptError):
+        rwpt.rwpt_create(cfg)
+
+
+def test_create_accepts_infinite_kappa_and_touches_no_device(lib):
+    cfg = rwpt.rwpt_config_default()
+    cfg.kappa = math.inf
+    ctx = rwpt.rwpt_create(cfg)
+    rwpt.rwpt_destroy(ctx)
+
+
+def test_validation_before_device(lib):
+    ctx = rwpt.rwpt_create(rwpt.rwpt_config_default())
+    try:
+        x = np.full((4, 2), 0.5)
+        M = np.ones((2, 4))
+        # state errors
+        with pytest.raises(rwpt.RwptError) as ei:
+            rwpt.rwpt_step(ctx, 0.1, 1e-5, 1)
+        assert ei.value.status == rwpt.RWPT_ESTATE
+        with pytest.raises(rwpt.RwptError) as ei:
+            rwpt.rwpt_step(ctx, 0.0, 1e-5, 1)
+        assert ei.value.status == rwpt.RWPT_EINVAL
+        with pytest.raises(rwpt.RwptError) as ei:
+            rwpt.rwpt_step(ctx, 0.1, -1.0, 1)
+        assert ei.value.status == rwpt.RWPT_EINVAL
+        # input errors are reported before any device call
+        bad = x.copy()
+        bad[2, 1] = 1.5
+        with pytest.raises(rwpt.RwptError) as ei:
+            rwpt.rwpt_init_ensemble(ctx, [4], bad, M)
+        assert ei.value.status == rwpt.RWPT_EINVAL and "outside" in str(ei.value)
+        bad = x.copy()
+        bad[0, 0] = float("nan")
+        with pytest.raises(rwpt.RwptError):
+            rwpt.rwpt_init_ensemble(ctx, [4], bad, M)
+        badm = M.copy()
+        badm[1, 3] = float("inf")
+        with pytest.raises(rwpt.RwptError):
+            rwpt.rwpt_init_ensemble(ctx, [4], x, badm)
+        with pytest.raises(rwpt.RwptError):
+            rwpt.rwpt_init_ensemble(ctx, [-1, 5], np.full((4, 2), 0.5), np.ones((2, 4)))
+        with pytest.raises(rwpt.RwptError):
+            rwpt.rwpt_init_ensemble(ctx, [4], x, M, d_scale=[-2.0])
+    finally:
+        rwpt.rwpt_destroy(ctx)
+
+
+def test_valid_init_without_gpu_reports_device_error(lib):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except Exception:
+        pass
+    ctx = rwpt.rwpt_create(rwpt.rwpt_config_default())
+    try:
+        with pytest.raises(rwpt.RwptError) as ei:
+            rwpt.rwpt_init_ensemble(ctx, [4], np.full((4, 2), 0.5), np.ones((2, 4)))
+        assert ei.value.status == rwpt.RWPT_EDEVICE
+    finally:
+        rwpt.rwpt_destroy(ctx)
+
+
+def test_destroy_null_is_allowed(lib):
+    lib.rwpt_destroy(None)
