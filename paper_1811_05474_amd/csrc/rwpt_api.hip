@@ -75,13 +75,15 @@ struct rwpt_ctx {
   DevBuf pos0, pos1, mass0, mass1, id, key, slot, tmp_src, tmp_id, tmp_key, skey, r, q;
   DevBuf cell_count, cell_start, scan_part;
   DevBuf d_rp, d_st, d_tiles, d_tile_start, d_real_start;
-  DevBuf audit_part, audit_out, step_ctr, counts;
+  DevBuf audit_part, audit_out, step_ctr, counts, d_chunks, d_chunk_start, chunk_part, audit_done;
   int64_t ncell_total = 0;
 
   std::vector<RealParams> h_rp;
   std::vector<StencilRow> h_st;
   std::vector<Tile> h_tiles;
   std::vector<int32_t> h_tile_start;
+  std::vector<int2> h_chunks;
+  std::vector<int32_t> h_chunk_start;
   int32_t ntiles = 0;
   int log2l = 3;
   double refine[3] = {0, 0, 0};
@@ -142,14 +144,23 @@ static int lanes_to_log2(int lanes) {
 
 static void default_refine(int dim, double out[3]) {
   // cells per cutoff length: fine along x (the fastest key axis, which trims
-  // the candidate ranges), about one cutoff across the other axes
+  // the candidate ranges), a few per cutoff across the other axes
   if (dim == 1) {
-    out[0] = 8.0; out[1] = 1.0; out[2] = 1.0;
+    out[0] = 16.0; out[1] = 1.0; out[2] = 1.0;
   } else if (dim == 2) {
-    out[0] = 4.0; out[1] = 2.0; out[2] = 1.0;
+    out[0] = 8.0; out[1] = 3.0; out[2] = 1.0;
   } else {
-    out[0] = 2.0; out[1] = 1.0; out[2] = 1.0;
+    out[0] = 4.0; out[1] = 1.0; out[2] = 1.0;
   }
+}
+
+// Lanes per particle when the configuration leaves it open: enough tiles to
+// fill the chip for small ensembles, fewer lanes per particle (smaller
+// candidate unions per lane) otherwise.
+static int default_lanes(int dim, int64_t n) {
+  if (dim == 1) return 16;
+  if (dim == 3) return 4;
+  return n >= (int64_t)1 << 19 ? 4 : 8;
 }
 
 static void invalidate_graphs(rwpt_ctx* c) {
@@ -184,6 +195,9 @@ static rwpt_status ensure_device(rwpt_ctx* c) {
     c->own_stream = true;
   }
   HIPCHK(c, c->step_ctr.ensure(sizeof(uint64_t)));
+  HIPCHK(c, c->audit_done.ensure(sizeof(uint32_t)));
+  HIPCHK(c, hipMemsetAsync(c->audit_done.p, 0, sizeof(uint32_t), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   c->device_ready = true;
   return RWPT_OK;
 }
@@ -239,7 +253,7 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   if (c->grid_valid && c->g_dt == dt && c->g_D == D) return RWPT_OK;
   const rwpt_config& cfg = c->cfg;
   const int dim = c->dim;
-  int lanes = cfg.tile_lanes ? cfg.tile_lanes : 8;
+  int lanes = cfg.tile_lanes ? cfg.tile_lanes : default_lanes(dim, c->N);
   c->log2l = lanes_to_log2(lanes);
   double defr[3];
   default_refine(dim, defr);
@@ -330,6 +344,14 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
       c->h_tiles.push_back(Tile{(int32_t)b, (int32_t)std::min<int64_t>(b + G, P.p_end), r, 0});
   }
   c->h_tile_start[c->n_real] = (int32_t)c->h_tiles.size();
+  c->h_chunks.clear();
+  c->h_chunk_start.assign(c->n_real + 1, 0);
+  for (int r = 0; r < c->n_real; ++r) {
+    c->h_chunk_start[r] = (int32_t)c->h_chunks.size();
+    for (int32_t t = c->h_tile_start[r]; t < c->h_tile_start[r + 1]; t += kAuditChunk)
+      c->h_chunks.push_back(make_int2(t, std::min<int32_t>(t + kAuditChunk, c->h_tile_start[r + 1])));
+  }
+  c->h_chunk_start[c->n_real] = (int32_t)c->h_chunks.size();
   if (cell_off >= (int64_t)1 << 31) return fail(c, RWPT_EUNSUPPORTED, "cell grid too large (%lld cells)", (long long)cell_off);
   c->ntiles = (int32_t)c->h_tiles.size();
 
@@ -346,6 +368,14 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   HIPCHK(c, c->d_tile_start.ensure(c->h_tile_start.size() * sizeof(int32_t)));
   HIPCHK(c, c->audit_part.ensure((size_t)std::max(1, c->ntiles) * (c->S + 1) * sizeof(double)));
   HIPCHK(c, c->counts.ensure((size_t)std::max(1, c->ntiles) * 2 * sizeof(unsigned long long)));
+  HIPCHK(c, c->d_chunks.ensure(std::max<size_t>(1, c->h_chunks.size()) * sizeof(int2)));
+  HIPCHK(c, c->d_chunk_start.ensure(c->h_chunk_start.size() * sizeof(int32_t)));
+  HIPCHK(c, c->chunk_part.ensure(std::max<size_t>(1, c->h_chunks.size()) * (c->S + 1) * sizeof(double)));
+  if (!c->h_chunks.empty())
+    HIPCHK(c, hipMemcpyAsync(c->d_chunks.p, c->h_chunks.data(), c->h_chunks.size() * sizeof(int2),
+                             hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_chunk_start.p, c->h_chunk_start.data(),
+                           c->h_chunk_start.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_rp.p, c->h_rp.data(), c->h_rp.size() * sizeof(RealParams),
                            hipMemcpyHostToDevice, c->stream));
   if (!c->h_st.empty())
@@ -449,9 +479,10 @@ static rwpt_status enqueue_step(rwpt_ctx* c, bool sort, bool walk) {
   }
   {
     PhaseScope ps(c, PH_AUDIT);
-    HIPCHK(c, launch_audit_reduce(c->audit_part.as<double>(), c->S + 1, c->d_tile_start.as<int32_t>(),
-                                  c->n_real, c->audit_out.as<double>(), c->step_ctr.as<uint64_t>(), 1,
-                                  c->stream));
+    HIPCHK(c, launch_audit_reduce(c->audit_part.as<double>(), c->S + 1, c->d_chunks.as<int2>(),
+                                  (int32_t)c->h_chunks.size(), c->chunk_part.as<double>(),
+                                  c->d_chunk_start.as<int32_t>(), c->n_real, c->audit_out.as<double>(),
+                                  c->audit_done.as<uint32_t>(), c->step_ctr.as<uint64_t>(), 1, c->stream));
   }
   return RWPT_OK;
 }
@@ -599,8 +630,12 @@ rwpt_status rwpt_init_ensemble(rwpt_ctx* c, int32_t n_real, const int64_t* n_per
   const size_t ts = c->tsize, cap = (size_t)c->cap;
   HIPCHK(c, c->pos0.ensure(dim * cap * ts));
   HIPCHK(c, c->pos1.ensure(dim * cap * ts));
-  HIPCHK(c, c->mass0.ensure(S * cap * ts));
-  HIPCHK(c, c->mass1.ensure(S * cap * ts));
+  const int Sa = padded_species(S);
+  HIPCHK(c, c->mass0.ensure(Sa * cap * ts));
+  HIPCHK(c, c->mass1.ensure(Sa * cap * ts));
+  // padding species rows stay zero for the lifetime of the ensemble
+  HIPCHK(c, hipMemsetAsync(c->mass0.p, 0, Sa * cap * ts, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->mass1.p, 0, Sa * cap * ts, c->stream));
   HIPCHK(c, c->id.ensure(cap * 4));
   HIPCHK(c, c->key.ensure(cap * 4));
   HIPCHK(c, c->slot.ensure(cap * 4));
@@ -915,7 +950,7 @@ const char* rwpt_profile_phase_name(int32_t phase) {
 
 rwpt_status rwpt_get_tiling(rwpt_ctx* c, int32_t* tile_lanes, double* cell_refine3) {
   if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
-  int lanes = c->cfg.tile_lanes ? c->cfg.tile_lanes : 8;
+  int lanes = c->cfg.tile_lanes ? c->cfg.tile_lanes : default_lanes(c->dim, c->N);
   double defr[3];
   default_refine(c->dim, defr);
   if (tile_lanes) *tile_lanes = lanes;
@@ -949,7 +984,8 @@ void rwpt_destroy(rwpt_ctx* c) {
                       &c->tmp_src, &c->tmp_id, &c->tmp_key, &c->skey, &c->r, &c->q, &c->cell_count,
                       &c->cell_start, &c->scan_part, &c->d_rp, &c->d_st, &c->d_tiles,
                       &c->d_tile_start, &c->d_real_start, &c->audit_part, &c->audit_out,
-                      &c->step_ctr, &c->counts};
+                      &c->step_ctr, &c->counts, &c->d_chunks, &c->d_chunk_start, &c->chunk_part,
+                      &c->audit_done};
     for (DevBuf* b : bufs) b->release();
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }

@@ -48,6 +48,11 @@ hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
                         int64_t cap, const void* mass_in, void* mass_out, int32_t S,
                         uint32_t* id_out, uint32_t* skey, hipStream_t s);
 
+// Species rows the mass arrays hold for S species: the exchange kernel is
+// instantiated for 2, 4 or 8 species and reads every row of its instantiation,
+// so rows S..padded_species(S)-1 are allocated and kept at zero.
+inline int padded_species(int S) { return S <= 2 ? 2 : (S <= 4 ? 4 : 8); }
+
 // Pair kernels (one wave per tile).  log2l: lanes per particle = 1 << log2l.
 hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
@@ -55,10 +60,15 @@ hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStre
 hipError_t launch_nbr_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 hipError_t launch_nbr_fill(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 
-// Per-realisation FP64 reduction of the per-tile audit partials; optionally
-// advances the device step counter.
-hipError_t launch_audit_reduce(const double* part, int32_t S1, const int32_t* tile_start,
-                               int32_t n_real, double* out, uint64_t* step_ctr, int32_t bump,
+// Per-realisation FP64 reduction of the per-tile audit partials in two fixed-
+// order levels (chunks of at most kAuditChunk tiles inside one realisation,
+// then the chunks of each realisation) in one launch; `done` is a zeroed
+// completion counter the kernel returns to zero.  Optionally advances the
+// step counter.
+constexpr int kAuditChunk = 1024;
+hipError_t launch_audit_reduce(const double* part, int32_t S1, const int2* chunks, int32_t nchunks,
+                               double* chunk_part, const int32_t* chunk_start, int32_t n_real,
+                               double* out, uint32_t* done, uint64_t* step_ctr, int32_t bump,
                                hipStream_t s);
 
 }  // namespace rwpt

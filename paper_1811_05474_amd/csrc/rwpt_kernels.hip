@@ -108,6 +108,27 @@ __device__ __forceinline__ T sep2(const T xi[DIM], const T* __restrict__ pos, in
   return s;
 }
 
+template <typename T, int DIM>
+__device__ __forceinline__ T sep2v(const T xi[DIM], const T xj[DIM]) {
+#pragma clang fp contract(off)
+  const T d0 = xj[0] - xi[0];
+  T s = d0 * d0;
+  if constexpr (DIM > 1) {
+    const T d1 = xj[1] - xi[1];
+    s = s + d1 * d1;
+  }
+  if constexpr (DIM > 2) {
+    const T d2 = xj[2] - xi[2];
+    s = s + d2 * d2;
+  }
+  return s;
+}
+
+// Candidates per lane handled per unrolled block (their loads are issued
+// together; with one lane per particle they are consecutive and uniform, so
+// they merge into wide scalar loads).
+constexpr int kUnroll = 4;
+
 // Co-location weight exp(-s2 / sigma^2) (Eq. 3 without prefactor): binary32
 // uses the hardware exp2 with the scale -log2(e)/sigma^2; binary64 uses the
 // library exp.
@@ -210,10 +231,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restri
   if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
 
-// Single block: exclusive scan of the block partials in place; writes the
-// grand total to *grand.
+// Single block: exclusive scan of the block partials in place; the grand
+// total becomes start[n] (the end of the last cell).
 __global__ __launch_bounds__(kBlock) void k_scan_top(uint32_t* __restrict__ partials, int32_t nb,
-                                                     uint32_t* __restrict__ grand) {
+                                                     uint32_t* __restrict__ start, int64_t n) {
   __shared__ uint32_t sh[4];
   const int per = (nb + kBlock - 1) / kBlock;
   const int b0 = threadIdx.x * per;
@@ -229,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(uint32_t* __restrict__ part
       partials[b0 + i] = run;
       run += v;
     }
-  if (threadIdx.x == 0) *grand = total;
+  if (threadIdx.x == 0) start[n] = total;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t* __restrict__ cnt, int64_t n,
@@ -254,10 +275,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t* __restrict__ cn
       run += v[i];
       cnt[base + i] = 0u;  // ready for the next step's counting
     }
-}
-
-__global__ void k_scan_tail(uint32_t* __restrict__ start, int64_t n, const uint32_t* __restrict__ grand) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) start[n] = *grand;
 }
 
 // ---------------------------------------------------------------------------
@@ -355,14 +372,18 @@ __device__ __forceinline__ void for_tile_rows(const RealParams& P, const Stencil
 
 // Load the tile header and this lane's particle.
 template <int LOG2L>
-__device__ __forceinline__ bool tile_lane_setup(const PairArgs& a, TileLane& tl, Tile& tile) {
+__device__ __forceinline__ bool tile_lane_setup(const Tile* __restrict__ tiles, int32_t ntiles,
+                                                TileLane& tl, Tile& tile) {
   constexpr int G = 64 >> LOG2L;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // the wave index is uniform across the wave; say so, so that everything
+  // derived from the tile is kept in scalar registers and loaded through the
+  // scalar cache
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int t = blk * (kBlock / 64) + wave;
-  if (t >= a.ntiles) return false;
-  tile = a.tiles[t];
+  if (t >= ntiles) return false;
+  tile = tiles[t];
   tl.gi = lane & (G - 1);
   tl.gl = lane >> (6 - LOG2L);
   tl.n_in = tile.end - tile.begin;
@@ -371,36 +392,54 @@ __device__ __forceinline__ bool tile_lane_setup(const PairArgs& a, TileLane& tl,
   return true;
 }
 
+template <typename T, int DIM>
+__device__ __forceinline__ void lane_cell(const RealParams& P, const uint32_t* __restrict__ skey,
+                                          int32_t ii, TileLane& tl) {
+  const uint32_t lk = skey[ii] - (uint32_t)P.cell_off;
+  tl.cx = (int)(lk % (uint32_t)P.nc[0]);
+  tl.row = (int)(lk / (uint32_t)P.nc[0]);
+}
+
+// Row sums r_i = sum_{j in N(i)} w_ij (self included) and q_i = 1 / r_i:
+// the normalisation of the co-location weights.
 template <typename T, int DIM, int LOG2L>
-__global__ __launch_bounds__(kBlock) void k_rowsum(PairArgs a) {
+__global__ __launch_bounds__(kBlock) void k_rowsum(
+    const T* __restrict__ pos, const int64_t cap, const uint32_t* __restrict__ skey,
+    const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles, const int32_t ntiles,
+    const RealParams* __restrict__ rp, const StencilRow* __restrict__ st, double* __restrict__ r_out,
+    T* __restrict__ q_out) {
   constexpr int L = 1 << LOG2L;
   constexpr int G = 64 >> LOG2L;
   TileLane tl;
   Tile tile;
-  if (!tile_lane_setup<LOG2L>(a, tl, tile)) return;
-  const RealParams& P = a.rp[tile.real];
-  const T* __restrict__ pos = (const T*)a.pos;
-  const int64_t cap = a.cap;
+  if (!tile_lane_setup<LOG2L>(tiles, ntiles, tl, tile)) return;
+  const RealParams& P = rp[tile.real];
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   T xi[DIM];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
-  const uint32_t lk = a.skey[ii] - (uint32_t)P.cell_off;
-  tl.cx = (int)(lk % (uint32_t)P.nc[0]);
-  tl.row = (int)(lk / (uint32_t)P.nc[0]);
+  lane_cell<T, DIM>(P, skey, ii, tl);
   const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
   double acc = 0.0;
   if (P.active) {
-    for_tile_rows<LOG2L>(P, a.st, a.cell_start, tl, [&](uint32_t jb, uint32_t je, bool act) {
+    for_tile_rows<LOG2L>(P, st, cell_start, tl, [&](uint32_t jb, uint32_t je, bool act) {
       T accr = (T)0;
-      const uint32_t len = je - jb, nfull = len >> LOG2L, rem = len & (L - 1);
+      const uint32_t len = je - jb, nblk = len / (L * kUnroll);
       uint32_t j = jb + tl.gl;
-      for (uint32_t c = 0; c < nfull; ++c, j += L) {
-        const T s2 = sep2<T, DIM>(xi, pos, cap, j);
-        const T w = kweight(s2, esc);
-        accr += (act && s2 <= rc2) ? w : (T)0;
+      for (uint32_t b = 0; b < nblk; ++b, j += L * kUnroll) {
+        T xj[kUnroll][DIM];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) xj[u][k] = pos[k * cap + j + u * L];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          const T s2 = sep2v<T, DIM>(xi, xj[u]);
+          const T w = kweight(s2, esc);
+          accr += (act && s2 <= rc2) ? w : (T)0;
+        }
       }
-      if (rem && (uint32_t)tl.gl < rem) {
+      for (; j < je; j += L) {
         const T s2 = sep2<T, DIM>(xi, pos, cap, j);
         const T w = kweight(s2, esc);
         accr += (act && s2 <= rc2) ? w : (T)0;
@@ -414,82 +453,119 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(PairArgs a) {
   for (int off = G; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
   if (tl.gl == 0 && tl.valid) {
     if (!P.active) acc = 1.0;
-    a.r_out[tl.i] = acc;
-    ((T*)a.q_out)[tl.i] = (T)(1.0 / acc);
+    r_out[tl.i] = acc;
+    q_out[tl.i] = (T)(1.0 / acc);
   }
 }
 
+// Weights + exchange (Eq. 4) + explicit update (Eq. 6) + reaction + audit
+// partials.  Symmetric normalisation: dM_i = 1/4 sum_j w_ij (q_i + q_j)(M_j - M_i);
+// row normalisation: dM_i = 1/2 (sum_j w_ij (M_j - M_i)) / r_i.
 template <typename T, int DIM, int SMAX, int LOG2L>
-__global__ __launch_bounds__(kBlock) void k_exchange(PairArgs a) {
+__global__ __launch_bounds__(kBlock) void k_exchange(
+    const T* __restrict__ pos, const int64_t cap, const T* __restrict__ min_, T* __restrict__ mout,
+    const T* __restrict__ q, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ cell_start,
+    const Tile* __restrict__ tiles, const int32_t ntiles, const RealParams* __restrict__ rp,
+    const StencilRow* __restrict__ st, const int32_t S, const int32_t react_a, const int32_t react_b,
+    const int32_t norm, double* __restrict__ audit_part) {
   constexpr int L = 1 << LOG2L;
   constexpr int G = 64 >> LOG2L;
   TileLane tl;
   Tile tile;
-  if (!tile_lane_setup<LOG2L>(a, tl, tile)) return;
-  const RealParams& P = a.rp[tile.real];
-  const T* __restrict__ pos = (const T*)a.pos;
-  const T* __restrict__ min_ = (const T*)a.mass_in;
-  const T* __restrict__ q = (const T*)a.q_in;
-  const int64_t cap = a.cap;
-  const int S = a.S;
+  if (!tile_lane_setup<LOG2L>(tiles, ntiles, tl, tile)) return;
+  const RealParams& P = rp[tile.real];
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   T xi[DIM];
 #pragma unroll
   for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
   T Mi[SMAX];
 #pragma unroll
-  for (int s = 0; s < SMAX; ++s) Mi[s] = (s < S) ? min_[s * cap + ii] : (T)0;
-  const uint32_t lk = a.skey[ii] - (uint32_t)P.cell_off;
-  tl.cx = (int)(lk % (uint32_t)P.nc[0]);
-  tl.row = (int)(lk / (uint32_t)P.nc[0]);
+  for (int s = 0; s < SMAX; ++s) Mi[s] = min_[s * cap + ii];
+  lane_cell<T, DIM>(P, skey, ii, tl);
   const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
   double acc[SMAX];
 #pragma unroll
   for (int s = 0; s < SMAX; ++s) acc[s] = 0.0;
   double racc = 0.0;
-  const bool sym = (a.norm == 0);
+  const bool sym = (norm == 0);
   if (P.active) {
     if (sym) {
       const T qi = q[ii];
-      for_tile_rows<LOG2L>(P, a.st, a.cell_start, tl, [&](uint32_t jb, uint32_t je, bool act) {
+      for_tile_rows<LOG2L>(P, st, cell_start, tl, [&](uint32_t jb, uint32_t je, bool act) {
         T accr[SMAX];
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) accr[s] = (T)0;
-        const uint32_t len = je - jb, nfull = len >> LOG2L, rem = len & (L - 1);
+        const uint32_t len = je - jb, nblk = len / (L * kUnroll);
         uint32_t j = jb + tl.gl;
-        auto body = [&](uint32_t jj) {
-          const T s2 = sep2<T, DIM>(xi, pos, cap, jj);
+        // species rows S..SMAX-1 exist and hold zeros, so no guard is needed
+        auto eval = [&](const T xj[DIM], T qj, const T mj[SMAX]) {
+          const T s2 = sep2v<T, DIM>(xi, xj);
           T w = kweight(s2, esc);
           w = (act && s2 <= rc2) ? w : (T)0;
-          const T p = w * (qi + q[jj]);  // 2 * symmetric P_ij
+          const T p = w * (qi + qj);  // 2 * symmetric P_ij
 #pragma unroll
-          for (int s = 0; s < SMAX; ++s)
-            if (s < S) accr[s] += p * (min_[s * cap + jj] - Mi[s]);
+          for (int s = 0; s < SMAX; ++s) accr[s] += p * (mj[s] - Mi[s]);
         };
-        for (uint32_t c = 0; c < nfull; ++c, j += L) body(j);
-        if (rem && (uint32_t)tl.gl < rem) body(j);
+        for (uint32_t b = 0; b < nblk; ++b, j += L * kUnroll) {
+          T xj[kUnroll][DIM], qj[kUnroll], mj[kUnroll][SMAX];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) xj[u][k] = pos[k * cap + j + u * L];
+            qj[u] = q[j + u * L];
+#pragma unroll
+            for (int s = 0; s < SMAX; ++s) mj[u][s] = min_[s * cap + j + u * L];
+          }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) eval(xj[u], qj[u], mj[u]);
+        }
+        for (; j < je; j += L) {
+          T xj[DIM], mj[SMAX];
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) xj[k] = pos[k * cap + j];
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s) mj[s] = min_[s * cap + j];
+          eval(xj, q[j], mj);
+        }
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
       });
     } else {
-      for_tile_rows<LOG2L>(P, a.st, a.cell_start, tl, [&](uint32_t jb, uint32_t je, bool act) {
+      for_tile_rows<LOG2L>(P, st, cell_start, tl, [&](uint32_t jb, uint32_t je, bool act) {
         T accr[SMAX];
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) accr[s] = (T)0;
         T rr = (T)0;
-        const uint32_t len = je - jb, nfull = len >> LOG2L, rem = len & (L - 1);
+        const uint32_t len = je - jb, nblk = len / (L * kUnroll);
         uint32_t j = jb + tl.gl;
-        auto body = [&](uint32_t jj) {
-          const T s2 = sep2<T, DIM>(xi, pos, cap, jj);
+        auto eval = [&](const T xj[DIM], const T mj[SMAX]) {
+          const T s2 = sep2v<T, DIM>(xi, xj);
           T w = kweight(s2, esc);
           w = (act && s2 <= rc2) ? w : (T)0;
           rr += w;
 #pragma unroll
-          for (int s = 0; s < SMAX; ++s)
-            if (s < S) accr[s] += w * (min_[s * cap + jj] - Mi[s]);
+          for (int s = 0; s < SMAX; ++s) accr[s] += w * (mj[s] - Mi[s]);
         };
-        for (uint32_t c = 0; c < nfull; ++c, j += L) body(j);
-        if (rem && (uint32_t)tl.gl < rem) body(j);
+        for (uint32_t b = 0; b < nblk; ++b, j += L * kUnroll) {
+          T xj[kUnroll][DIM], mj[kUnroll][SMAX];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) xj[u][k] = pos[k * cap + j + u * L];
+#pragma unroll
+            for (int s = 0; s < SMAX; ++s) mj[u][s] = min_[s * cap + j + u * L];
+          }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) eval(xj[u], mj[u]);
+        }
+        for (; j < je; j += L) {
+          T xj[DIM], mj[SMAX];
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) xj[k] = pos[k * cap + j];
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s) mj[s] = min_[s * cap + j];
+          eval(xj, mj);
+        }
 #pragma unroll
         for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
         racc += (double)rr;
@@ -514,13 +590,13 @@ __global__ __launch_bounds__(kBlock) void k_exchange(PairArgs a) {
       if (P.active) dm = sym ? 0.25 * acc[s] : 0.5 * acc[s] / racc;
       Mn[s] = (double)Mi[s] + dm;
     }
-    if (a.react_a >= 0) {
+    if (react_a >= 0) {
 #pragma unroll
       for (int s = 0; s < SMAX; ++s)
-        if (s == a.react_a) {
+        if (s == react_a) {
 #pragma unroll
           for (int t2 = 0; t2 < SMAX; ++t2)
-            if (t2 == a.react_b) {
+            if (t2 == react_b) {
               double m = Mn[s] < Mn[t2] ? Mn[s] : Mn[t2];
               m = m > 0.0 ? m : 0.0;
               Mn[s] -= m;
@@ -528,7 +604,6 @@ __global__ __launch_bounds__(kBlock) void k_exchange(PairArgs a) {
             }
         }
     }
-    T* __restrict__ mout = (T*)a.mass_out;
     double va = 0.0, vb = 0.0;
 #pragma unroll
     for (int s = 0; s < SMAX; ++s)
@@ -536,8 +611,8 @@ __global__ __launch_bounds__(kBlock) void k_exchange(PairArgs a) {
         const T v = (T)Mn[s];
         mout[s * cap + tl.i] = v;
         tot[s] = (double)v;
-        if (s == a.react_a) va = (double)v;
-        if (s == a.react_b) vb = (double)v;
+        if (s == react_a) va = (double)v;
+        if (s == react_b) vb = (double)v;
       }
     tot[SMAX] = va - vb;
   }
@@ -549,7 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange(PairArgs a) {
   }
   if ((threadIdx.x & 63) == 0) {
     const int t = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
-    double* part = a.audit_part + (int64_t)t * (S + 1);
+    double* part = audit_part + (int64_t)t * (S + 1);
     for (int s = 0; s < S; ++s) part[s] = tot[s < SMAX ? s : 0];
     part[S] = tot[SMAX];
   }
@@ -561,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_count(PairArgs a) {
   constexpr int L = 1 << LOG2L;
   TileLane tl;
   Tile tile;
-  if (!tile_lane_setup<LOG2L>(a, tl, tile)) return;
+  if (!tile_lane_setup<LOG2L>(a.tiles, a.ntiles, tl, tile)) return;
   const RealParams& P = a.rp[tile.real];
   const T* __restrict__ pos = (const T*)a.pos;
   const int64_t cap = a.cap;
@@ -608,7 +683,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr(PairArgs a) {
   constexpr int L = 1 << LOG2L;
   TileLane tl;
   Tile tile;
-  if (!tile_lane_setup<LOG2L>(a, tl, tile)) return;
+  if (!tile_lane_setup<LOG2L>(a.tiles, a.ntiles, tl, tile)) return;
   const RealParams& P = a.rp[tile.real];
   const T* __restrict__ pos = (const T*)a.pos;
   const int64_t cap = a.cap;
@@ -656,26 +731,59 @@ __global__ __launch_bounds__(kBlock) void k_nbr(PairArgs a) {
 // Audit
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_audit_reduce(const double* __restrict__ part, int32_t S1,
-                                                         const int32_t* __restrict__ tile_start,
-                                                         int32_t n_real, double* __restrict__ out,
-                                                         uint64_t* __restrict__ step_ctr, int32_t bump) {
-  __shared__ double sh[kBlock];
-  const int r = blockIdx.x;
-  const int t0 = tile_start[r], t1 = tile_start[r + 1];
-  for (int v = 0; v < S1; ++v) {
-    double s = 0.0;
-    for (int t = t0 + threadIdx.x; t < t1; t += kBlock) s += part[(int64_t)t * S1 + v];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[(int64_t)r * S1 + v] = sh[0];
+// Fixed-order block sum of v over the 256 threads (thread 0 gets the result).
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (bump && r == 0 && threadIdx.x == 0) *step_ctr = *step_ctr + 1;
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Audit in one launch: every block sums one chunk of at most kAuditChunk
+// consecutive tiles (never straddling realisations) in a fixed order; the
+// block that finishes last then sums, per realisation, its chunk partials in
+// chunk order, so the result does not depend on which block is last.  The
+// completion counter is returned to zero for the next launch.
+__global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ part, int32_t S1,
+                                                  const int2* __restrict__ chunks, int32_t nchunks,
+                                                  double* __restrict__ chunk_part,
+                                                  const int32_t* __restrict__ chunk_start, int32_t n_real,
+                                                  double* __restrict__ out, uint32_t* __restrict__ done,
+                                                  uint64_t* __restrict__ step_ctr, int32_t bump) {
+  __shared__ double sh[kBlock];
+  __shared__ bool last;
+  const int2 ch = chunks[blockIdx.x];
+  for (int v = 0; v < S1; ++v) {
+    double s = 0.0;
+    for (int t = ch.x + threadIdx.x; t < ch.y; t += kBlock) s += part[(int64_t)t * S1 + v];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) chunk_part[(int64_t)blockIdx.x * S1 + v] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(done, 1u) == (uint32_t)(nchunks - 1);
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (int r = 0; r < n_real; ++r) {
+    const int c0 = chunk_start[r], c1 = chunk_start[r + 1];
+    for (int v = 0; v < S1; ++v) {
+      double s = 0.0;
+      for (int c = c0 + threadIdx.x; c < c1; c += kBlock)
+        s += __hip_atomic_load(&chunk_part[(int64_t)c * S1 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s = block_sum(s, sh);
+      if (threadIdx.x == 0) out[(int64_t)r * S1 + v] = s;
+    }
+  }
+  if (threadIdx.x == 0) {
+    *done = 0u;
+    if (bump) *step_ctr = *step_ctr + 1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -711,10 +819,9 @@ hipError_t launch_cell_scan(uint32_t* cell_count, uint32_t* cell_start, int64_t 
                             uint32_t* partials, hipStream_t s) {
   const int64_t nb = (ncell + kScanChunk - 1) / kScanChunk;
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, cell_count, ncell, partials);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, partials, (int32_t)nb, partials + nb);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, partials, (int32_t)nb, cell_start, ncell);
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, cell_count, ncell, partials,
                      cell_start);
-  hipLaunchKernelGGL(k_scan_tail, dim3(1), dim3(64), 0, s, cell_start, ncell, partials + nb);
   return hipGetLastError();
 }
 
@@ -787,7 +894,8 @@ hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStr
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
   return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
     using T = decltype(t);
-    hipLaunchKernelGGL((k_rowsum<T, decltype(d)::value, decltype(l)::value>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_rowsum<T, decltype(d)::value, decltype(l)::value>), g, b, 0, s, (const T*)a.pos,
+                       a.cap, a.skey, a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (T*)a.q_out);
   });
 }
 
@@ -798,9 +906,13 @@ hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipS
   return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
     using T = decltype(t);
     constexpr int D = decltype(d)::value, L = decltype(l)::value;
-    if (a.S <= 2) hipLaunchKernelGGL((k_exchange<T, D, 2, L>), g, b, 0, s, a);
-    else if (a.S <= 4) hipLaunchKernelGGL((k_exchange<T, D, 4, L>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_exchange<T, D, 8, L>), g, b, 0, s, a);
+#define RWPT_EX_ARGS                                                                          \
+  (const T*)a.pos, a.cap, (const T*)a.mass_in, (T*)a.mass_out, (const T*)a.q_in, a.skey, a.cell_start, \
+      a.tiles, a.ntiles, a.rp, a.st, a.S, a.react_a, a.react_b, a.norm, a.audit_part
+    if (a.S <= 2) hipLaunchKernelGGL((k_exchange<T, D, 2, L>), g, b, 0, s, RWPT_EX_ARGS);
+    else if (a.S <= 4) hipLaunchKernelGGL((k_exchange<T, D, 4, L>), g, b, 0, s, RWPT_EX_ARGS);
+    else hipLaunchKernelGGL((k_exchange<T, D, 8, L>), g, b, 0, s, RWPT_EX_ARGS);
+#undef RWPT_EX_ARGS
   });
 }
 
@@ -831,12 +943,13 @@ hipError_t launch_nbr_fill(int fp64, int dim, int log2l, const PairArgs& a, hipS
   });
 }
 
-hipError_t launch_audit_reduce(const double* part, int32_t S1, const int32_t* tile_start,
-                               int32_t n_real, double* out, uint64_t* step_ctr, int32_t bump,
+hipError_t launch_audit_reduce(const double* part, int32_t S1, const int2* chunks, int32_t nchunks,
+                               double* chunk_part, const int32_t* chunk_start, int32_t n_real,
+                               double* out, uint32_t* done, uint64_t* step_ctr, int32_t bump,
                                hipStream_t s) {
-  if (n_real <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_audit_reduce, dim3((unsigned)n_real), dim3(kBlock), 0, s, part, S1, tile_start,
-                     n_real, out, step_ctr, bump);
+  if (n_real <= 0 || nchunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_audit, dim3((unsigned)nchunks), dim3(kBlock), 0, s, part, S1, chunks, nchunks,
+                     chunk_part, chunk_start, n_real, out, done, step_ctr, bump);
   return hipGetLastError();
 }
 
