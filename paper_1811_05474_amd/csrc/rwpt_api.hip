@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -959,12 +960,189 @@ rwpt_status rwpt_get_tiling(rwpt_ctx* c, int32_t* tile_lanes, double* cell_refin
   return RWPT_OK;
 }
 
+// Candidate tilings per dimension: lanes per particle x cells per cutoff.
+static std::vector<std::pair<int, std::array<double, 3>>> tuning_candidates(int dim) {
+  std::vector<std::array<double, 3>> refs;
+  if (dim == 1) refs = {{4, 1, 1}, {8, 1, 1}, {16, 1, 1}, {32, 1, 1}};
+  else if (dim == 2) refs = {{8, 1, 1}, {16, 1, 1}, {4, 2, 1}, {8, 2, 1}, {8, 3, 1}, {16, 3, 1}, {8, 4, 1}};
+  else refs = {{2, 1, 1}, {4, 1, 1}, {8, 1, 1}, {4, 2, 2}, {8, 0.5, 0.5}, {16, 0.5, 0.5}};
+  std::vector<std::pair<int, std::array<double, 3>>> out;
+  for (int lanes : {1, 4, 8, 16})
+    for (auto& r : refs) out.push_back({lanes, r});
+  return out;
+}
+
+static std::string tuning_key(const rwpt_ctx* c, double dt, double D) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "dim=%d N=%lld S=%d nreal=%d D=%.6g dt=%.6g kappa=%.6g prec=%d norm=%d rw=%.6g",
+           c->dim, (long long)c->N, c->S, c->n_real, D, dt, c->cfg.kappa, c->cfg.precision, c->cfg.norm,
+           c->cfg.rw_ratio);
+  return buf;
+}
+
+static bool tuning_cache_lookup(const std::string& key, int* lanes, double ref[3]) {
+  const char* path = getenv("RWPT_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    char* bar = strchr(line, '|');
+    if (!bar) continue;
+    *bar = 0;
+    if (key == line) {
+      int l;
+      double r0, r1, r2;
+      if (sscanf(bar + 1, "%d %lf %lf %lf", &l, &r0, &r1, &r2) == 4 && lanes_to_log2(l) >= 0) {
+        *lanes = l;
+        ref[0] = r0;
+        ref[1] = r1;
+        ref[2] = r2;
+        found = true;
+      }
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+static void tuning_cache_store(const std::string& key, int lanes, const double ref[3]) {
+  const char* path = getenv("RWPT_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s|%d %.17g %.17g %.17g\n", key.c_str(), lanes, ref[0], ref[1], ref[2]);
+  fclose(f);
+}
+
 rwpt_status rwpt_autotune(rwpt_ctx* c, double dt, double D, int32_t trial_steps) {
   if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
-  (void)dt;
-  (void)D;
-  (void)trial_steps;
-  return fail(c, RWPT_EUNSUPPORTED, "autotuning is not available in this build");
+  c->err.clear();
+  if (!std::isfinite(dt) || dt <= 0.0 || !std::isfinite(D) || D < 0.0)
+    return fail(c, RWPT_EINVAL, "dt must be > 0 and D >= 0");
+  if (trial_steps < 1 || trial_steps > 1000) return fail(c, RWPT_EINVAL, "trial_steps must be in 1..1000");
+  if (!c->initialized) return fail(c, RWPT_ESTATE, "autotune before rwpt_init_ensemble");
+  if (c->N == 0) return RWPT_OK;
+  const std::string key = tuning_key(c, dt, D);
+  int best_lanes = 0;
+  double best_ref[3] = {0, 0, 0};
+  if (tuning_cache_lookup(key, &best_lanes, best_ref)) {
+    c->cfg.tile_lanes = best_lanes;
+    for (int k = 0; k < 3; ++k) c->cfg.cell_refine[k] = best_ref[k];
+    c->grid_valid = false;
+    c->sorted_valid = false;
+    invalidate_graphs(c);
+    return RWPT_OK;
+  }
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  // snapshot of the state the tuning steps will overwrite
+  const size_t ts = c->tsize, cap = (size_t)c->cap;
+  const int Sa = padded_species(c->S);
+  const size_t npos = c->dim * cap * ts, nmass = Sa * cap * ts, naud = (size_t)c->n_real * (c->S + 1) * 8;
+  DevBuf sp, sm, si, sa, sc;
+  rwpt_status result = RWPT_OK;
+  const rwpt_config saved_cfg = c->cfg;
+  const int64_t saved_steps = c->steps;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  do {
+    if (sp.ensure(npos) != hipSuccess || sm.ensure(nmass) != hipSuccess || si.ensure(cap * 4) != hipSuccess ||
+        sa.ensure(naud) != hipSuccess || sc.ensure(8) != hipSuccess) {
+      result = fail(c, RWPT_ENOMEM, "autotune snapshot");
+      break;
+    }
+    hipError_t e = hipMemcpyAsync(sp.p, c->pos0.p, npos, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(sm.p, c->mass0.p, nmass, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(si.p, c->id.p, cap * 4, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(sa.p, c->audit_out.p, naud, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(sc.p, c->step_ctr.p, 8, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+      result = fail(c, RWPT_EDEVICE, "autotune setup: %s", hipGetErrorString(e));
+      break;
+    }
+    auto restore = [&]() -> hipError_t {
+      hipError_t r = hipMemcpyAsync(c->pos0.p, sp.p, npos, hipMemcpyDeviceToDevice, c->stream);
+      if (r == hipSuccess) r = hipMemcpyAsync(c->mass0.p, sm.p, nmass, hipMemcpyDeviceToDevice, c->stream);
+      if (r == hipSuccess) r = hipMemcpyAsync(c->id.p, si.p, cap * 4, hipMemcpyDeviceToDevice, c->stream);
+      if (r == hipSuccess) r = hipMemcpyAsync(c->audit_out.p, sa.p, naud, hipMemcpyDeviceToDevice, c->stream);
+      if (r == hipSuccess) r = hipMemcpyAsync(c->step_ctr.p, sc.p, 8, hipMemcpyDeviceToDevice, c->stream);
+      c->steps = saved_steps;
+      c->grid_valid = false;
+      c->sorted_valid = false;
+      invalidate_graphs(c);
+      return r;
+    };
+    float best_ms = INFINITY;
+    const bool was_prof = c->prof;
+    c->prof = false;
+    for (auto& cand : tuning_candidates(c->dim)) {
+      c->cfg.tile_lanes = cand.first;
+      for (int k = 0; k < 3; ++k) c->cfg.cell_refine[k] = cand.second[k];
+      if (restore() != hipSuccess) {
+        result = fail(c, RWPT_EDEVICE, "autotune restore");
+        break;
+      }
+      rwpt_status st = rwpt_step(c, dt, D, 1);  // builds the grid, sorts, captures graphs
+      if (st != RWPT_OK) {
+        result = st;
+        break;
+      }
+      e = hipEventRecord(e0, c->stream);
+      st = rwpt_step(c, dt, D, trial_steps);
+      if (st != RWPT_OK) {
+        result = st;
+        break;
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        result = fail(c, RWPT_EDEVICE, "autotune timing: %s", hipGetErrorString(e));
+        break;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best_lanes = cand.first;
+        for (int k = 0; k < 3; ++k) best_ref[k] = cand.second[k];
+      }
+    }
+    c->prof = was_prof;
+    if (result != RWPT_OK) break;
+    c->cfg.tile_lanes = best_lanes;
+    for (int k = 0; k < 3; ++k) c->cfg.cell_refine[k] = best_ref[k];
+    if (restore() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+      result = fail(c, RWPT_EDEVICE, "autotune final restore");
+      break;
+    }
+    tuning_cache_store(key, best_lanes, best_ref);
+  } while (0);
+  if (result != RWPT_OK) {
+    // leave the context usable with the caller's original tiling and state
+    c->cfg = saved_cfg;
+    if (sp.p && sm.p && si.p && sa.p && sc.p) {
+      (void)hipMemcpyAsync(c->pos0.p, sp.p, npos, hipMemcpyDeviceToDevice, c->stream);
+      (void)hipMemcpyAsync(c->mass0.p, sm.p, nmass, hipMemcpyDeviceToDevice, c->stream);
+      (void)hipMemcpyAsync(c->id.p, si.p, cap * 4, hipMemcpyDeviceToDevice, c->stream);
+      (void)hipMemcpyAsync(c->audit_out.p, sa.p, naud, hipMemcpyDeviceToDevice, c->stream);
+      (void)hipMemcpyAsync(c->step_ctr.p, sc.p, 8, hipMemcpyDeviceToDevice, c->stream);
+    }
+    c->steps = saved_steps;
+    c->grid_valid = false;
+    c->sorted_valid = false;
+    invalidate_graphs(c);
+  }
+  (void)hipStreamSynchronize(c->stream);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  sp.release();
+  sm.release();
+  si.release();
+  sa.release();
+  sc.release();
+  return result;
 }
 
 const char* rwpt_last_error(const rwpt_ctx* c) {

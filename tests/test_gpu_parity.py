@@ -362,3 +362,37 @@ def test_bitwise_deterministic_and_resumable():
     # re-initialising from the queried state continues the same trajectory
     # when the step counter is carried (the walk draws depend on id, step, seed)
     e2.close()
+
+
+# -------------------------------------------------------------- autotuner ----
+
+def test_autotune_restores_state_and_keeps_parity(tmp_path, monkeypatch):
+    n, D, dt = 30000, 2e-4, 0.1
+    x = W.positions(n, 2, 41)
+    M = W.masses(n, 2, 41)
+    monkeypatch.setenv("RWPT_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    ens = make(dim=2, rw=1.0, prec=F32, seed=41)
+    ens.init([n], x, M)
+    ens.step(dt, D, 2)
+    m0, p0, a0, s0 = ens.masses(), ens.positions(), ens.audit(), ens.steps_taken()
+    rwpt.rwpt_autotune(ens.ctx, dt, D, 2)
+    assert np.array_equal(ens.masses(), m0) and np.array_equal(ens.positions(), p0)
+    assert np.array_equal(ens.audit(), a0) and ens.steps_taken() == s0
+    lanes, ref = rwpt.rwpt_get_tiling(ens.ctx)
+    assert lanes in (1, 4, 8, 16)
+    ens.step(dt, D, 1)
+    pos = ens.positions()
+    walked = oracle.walk(p0, np.arange(n), 41, s0, D, dt, (0, 0), (1, 1))
+    assert np.abs(pos - walked).max() < 2e-6
+    ref_m = oracle.transfer(pos, m0, D, dt, kappa=3.0, prec=32)
+    assert normerr(ens.masses(), ref_m) < 1e-5
+    ens.close()
+    # a second context with the same shape takes the cached choice
+    text = (tmp_path / "tune.txt").read_text()
+    assert text.count("|") == 1
+    e2 = make(dim=2, rw=1.0, prec=F32, seed=41)
+    e2.init([n], x, M)
+    rwpt.rwpt_autotune(e2.ctx, dt, D, 2)
+    assert rwpt.rwpt_get_tiling(e2.ctx) == (lanes, ref)
+    assert (tmp_path / "tune.txt").read_text() == text
+    e2.close()
