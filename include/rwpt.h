@@ -62,10 +62,15 @@ enum { RWPT_FP32 = 0, RWPT_FP64 = 1 };
  *      neighbourhoods differ. */
 enum { RWPT_NORM_SYM = 0, RWPT_NORM_ROW = 1 };
 
-/* Evaluation path.  SPARSE: cell-list neighbour search + per-pair kernels.
- * DENSE: every pair of a realisation on matrix cores (the full-matrix
- * "brute force" of Sec. 1.1); needs kappa = +inf and dim = 1.
- * AUTO: DENSE when allowed and kappa is infinite, else SPARSE. */
+/* Evaluation path.  SPARSE: cell-list neighbour search + per-pair kernels
+ * (any kappa, either precision).  DENSE: every pair of the realisation (the
+ * full-matrix "brute force" of Sec. 1.1) as a contraction on matrix cores:
+ * weight tiles generated from the positions, split into three bf16 parts and
+ * multiplied with the bf16-split mass columns with fp32 accumulation; needs
+ * kappa = INFINITY (checked at create), RWPT_FP32 (create), and one
+ * realisation of at most 131072 particles (init, else RWPT_EUNSUPPORTED).
+ * Pairs whose weight is below 2^-40 are skipped tile-wise.
+ * AUTO: DENSE when those conditions hold, else SPARSE. */
 enum { RWPT_PATH_AUTO = 0, RWPT_PATH_SPARSE = 1, RWPT_PATH_DENSE = 2 };
 
 typedef struct rwpt_config {

@@ -77,6 +77,9 @@ struct rwpt_ctx {
   DevBuf cell_count, cell_start, scan_part;
   DevBuf d_rp, d_st, d_tiles, d_tile_start, d_real_start;
   DevBuf audit_part, audit_out, step_ctr, counts, d_chunks, d_chunk_start, chunk_part, audit_done;
+  DevBuf bbox, bparts;  // full-matrix path
+  bool dense = false;   // full-matrix path selected at init
+  float dense_escale = 0.0f, dense_skip_s2 = 0.0f;
   int64_t ncell_total = 0;
 
   std::vector<RealParams> h_rp;
@@ -255,6 +258,7 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   const rwpt_config& cfg = c->cfg;
   const int dim = c->dim;
   int lanes = cfg.tile_lanes ? cfg.tile_lanes : default_lanes(dim, c->N);
+  if (c->dense) lanes = 64 / kDenseRowTile;  // tiles of 16 rows (audit partials, D = 0 copy)
   c->log2l = lanes_to_log2(lanes);
   double defr[3];
   default_refine(dim, defr);
@@ -292,6 +296,14 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
       P.escale_f = (float)(-1.4426950408889634073599246810019 / sigma2);
       // geometric cutoff: covers the rounding of s^2 in the predicate
       rcg = std::sqrt(rc2) * (1.0 + 1e-5);
+      if (c->dense) {
+        // every pair counts; the grid only orders particles so that 32-particle
+        // column tiles are compact, and tiles farther apart than the distance
+        // where w < 2^-40 are skipped
+        c->dense_escale = P.escale_f;
+        c->dense_skip_s2 = (float)(41.0 / std::fabs((double)P.escale_f));
+        rcg = std::sqrt(40.0 / std::fabs((double)P.escale_f));
+      }
       if (std::isfinite(rcg)) {
         for (int k = 0; k < dim; ++k) {
           double v = std::floor(L[k] * c->refine[k] / rcg);
@@ -318,7 +330,7 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
     P.cell_off = cell_off;
     cell_off += nc[0] * nc[1] * nc[2];
     P.stencil_off = (int32_t)c->h_st.size();
-    if (P.active) {
+    if (P.active && !c->dense) {
       const double h[3] = {L[0] / nc[0], L[1] / nc[1], L[2] / nc[2]};
       int Ry = 0, Rz = 0;
       if (dim >= 2) Ry = std::isfinite(rcg) ? (int)std::min<double>(nc[1] - 1, std::ceil(rcg / h[1])) : (int)nc[1] - 1;
@@ -369,6 +381,11 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   HIPCHK(c, c->d_tile_start.ensure(c->h_tile_start.size() * sizeof(int32_t)));
   HIPCHK(c, c->audit_part.ensure((size_t)std::max(1, c->ntiles) * (c->S + 1) * sizeof(double)));
   HIPCHK(c, c->counts.ensure((size_t)std::max(1, c->ntiles) * 2 * sizeof(unsigned long long)));
+  if (c->dense) {
+    const int ncb = dense_ncb(c->S, c->cfg.norm);
+    HIPCHK(c, c->bbox.ensure((size_t)(c->cap / kDenseColTile + 1) * 2 * c->dim * sizeof(float)));
+    HIPCHK(c, c->bparts.ensure((size_t)3 * 16 * ncb * c->cap * sizeof(uint16_t)));
+  }
   HIPCHK(c, c->d_chunks.ensure(std::max<size_t>(1, c->h_chunks.size()) * sizeof(int2)));
   HIPCHK(c, c->d_chunk_start.ensure(c->h_chunk_start.size() * sizeof(int32_t)));
   HIPCHK(c, c->chunk_part.ensure(std::max<size_t>(1, c->h_chunks.size()) * (c->S + 1) * sizeof(double)));
@@ -470,11 +487,33 @@ static rwpt_status enqueue_step(rwpt_ctx* c, bool sort, bool walk) {
                              hipMemcpyDeviceToDevice, c->stream));
   }
   PairArgs a = pair_args(c);
-  if (c->cfg.norm == RWPT_NORM_SYM) {
-    PhaseScope ps(c, PH_ROWSUM);
-    HIPCHK(c, launch_rowsum(fp64, c->dim, c->log2l, a, c->stream));
-  }
-  {
+  if (c->dense && c->h_rp[0].active) {
+    DenseArgs da;
+    memset(&da, 0, sizeof(da));
+    da.pos = c->pos0.as<float>();
+    da.cap = c->cap;
+    da.n = (int32_t)c->N;
+    da.mass_in = c->mass1.as<float>();
+    da.mass_out = c->mass0.as<float>();
+    da.q = c->q.as<float>();
+    da.r = c->r.as<double>();
+    da.bbox = c->bbox.as<float>();
+    da.escale = c->dense_escale;
+    da.skip_s2 = c->dense_skip_s2;
+    da.bparts = c->bparts.as<__bf16>();
+    da.ncb = dense_ncb(c->S, c->cfg.norm);
+    da.S = c->S;
+    da.react_a = c->cfg.react_a;
+    da.react_b = c->cfg.react_b;
+    da.norm = c->cfg.norm;
+    da.audit_part = c->audit_part.as<double>();
+    PhaseScope ps(c, PH_DENSE);
+    HIPCHK(c, launch_dense_step(c->dim, da, c->stream));
+  } else {
+    if (c->cfg.norm == RWPT_NORM_SYM) {
+      PhaseScope ps(c, PH_ROWSUM);
+      HIPCHK(c, launch_rowsum(fp64, c->dim, c->log2l, a, c->stream));
+    }
     PhaseScope ps(c, PH_EXCHANGE);
     HIPCHK(c, launch_exchange(fp64, c->dim, c->log2l, a, c->stream));
   }
@@ -556,8 +595,10 @@ rwpt_status rwpt_create(const rwpt_config* cfg, rwpt_ctx** out) {
     return fail(nullptr, RWPT_EINVAL, "norm must be RWPT_NORM_SYM or RWPT_NORM_ROW");
   if (c.path < RWPT_PATH_AUTO || c.path > RWPT_PATH_DENSE)
     return fail(nullptr, RWPT_EINVAL, "path must be AUTO, SPARSE or DENSE");
-  if (c.path == RWPT_PATH_DENSE)
-    return fail(nullptr, RWPT_EUNSUPPORTED, "the dense path is not available in this build");
+  if (c.path == RWPT_PATH_DENSE && !std::isinf(c.kappa))
+    return fail(nullptr, RWPT_EINVAL, "the dense path evaluates every pair: kappa must be INFINITY");
+  if (c.path == RWPT_PATH_DENSE && c.precision != RWPT_FP32)
+    return fail(nullptr, RWPT_EUNSUPPORTED, "the dense (matrix-core) path is binary32 only");
   if (c.tile_lanes != 0 && lanes_to_log2(c.tile_lanes) < 0)
     return fail(nullptr, RWPT_EINVAL, "tile_lanes must be 0, 1, 4, 8 or 16 (got %d)", c.tile_lanes);
   for (int k = 0; k < 3; ++k)
@@ -627,6 +668,13 @@ rwpt_status rwpt_init_ensemble(rwpt_ctx* c, int32_t n_real, const int64_t* n_per
   c->d_scale.assign(n_real, 1.0);
   if (d_scale)
     for (int r = 0; r < n_real; ++r) c->d_scale[r] = d_scale[r];
+  // full-matrix path on matrix cores: one realisation, binary32, kappa = inf
+  const bool dense_ok = std::isinf(c->cfg.kappa) && c->cfg.precision == RWPT_FP32 && n_real == 1 &&
+                        N <= kDenseMaxN;
+  if (c->cfg.path == RWPT_PATH_DENSE && !dense_ok)
+    return fail(c, RWPT_EUNSUPPORTED, "the dense path needs one realisation of at most %lld particles",
+                (long long)kDenseMaxN);
+  c->dense = dense_ok && c->cfg.path != RWPT_PATH_SPARSE;
   c->cap = std::max<int64_t>(64, (N + 63) / 64 * 64);
   const size_t ts = c->tsize, cap = (size_t)c->cap;
   HIPCHK(c, c->pos0.ensure(dim * cap * ts));
@@ -825,6 +873,13 @@ rwpt_status rwpt_count_pairs(rwpt_ctx* c, double dt, double D, int64_t* pairs_ou
   *pairs_out = 0;
   if (evals_out) *evals_out = 0;
   if (c->N == 0) return RWPT_OK;
+  if (c->dense) {
+    // the full-matrix path evaluates every ordered pair of the realisation
+    const int64_t n = c->N;
+    *pairs_out = D > 0.0 ? n * (n - 1) : 0;
+    if (evals_out) *evals_out = D > 0.0 ? n * n : 0;
+    return RWPT_OK;
+  }
   rwpt_status st = build_grid(c, dt, D);
   if (st != RWPT_OK) return st;
   st = ensure_sorted(c);
@@ -860,6 +915,7 @@ rwpt_status rwpt_neighbors(rwpt_ctx* c, double dt, double D, int64_t* rowptr, in
     if (rowptr) rowptr[0] = 0;
     return RWPT_OK;
   }
+  if (c->dense) return fail(c, RWPT_EUNSUPPORTED, "the full-matrix path has no neighbour lists (every pair)");
   rwpt_status st = build_grid(c, dt, D);
   if (st != RWPT_OK) return st;
   st = ensure_sorted(c);
@@ -1023,7 +1079,7 @@ rwpt_status rwpt_autotune(rwpt_ctx* c, double dt, double D, int32_t trial_steps)
     return fail(c, RWPT_EINVAL, "dt must be > 0 and D >= 0");
   if (trial_steps < 1 || trial_steps > 1000) return fail(c, RWPT_EINVAL, "trial_steps must be in 1..1000");
   if (!c->initialized) return fail(c, RWPT_ESTATE, "autotune before rwpt_init_ensemble");
-  if (c->N == 0) return RWPT_OK;
+  if (c->N == 0 || c->dense) return RWPT_OK;
   const std::string key = tuning_key(c, dt, D);
   int best_lanes = 0;
   double best_ref[3] = {0, 0, 0};
@@ -1163,7 +1219,7 @@ void rwpt_destroy(rwpt_ctx* c) {
                       &c->cell_start, &c->scan_part, &c->d_rp, &c->d_st, &c->d_tiles,
                       &c->d_tile_start, &c->d_real_start, &c->audit_part, &c->audit_out,
                       &c->step_ctr, &c->counts, &c->d_chunks, &c->d_chunk_start, &c->chunk_part,
-                      &c->audit_done};
+                      &c->audit_done, &c->bbox, &c->bparts};
     for (DevBuf* b : bufs) b->release();
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }

@@ -71,4 +71,28 @@ hipError_t launch_audit_reduce(const double* part, int32_t S1, const int2* chunk
                                double* out, uint32_t* done, uint64_t* step_ctr, int32_t bump,
                                hipStream_t s);
 
+// Full-matrix path of one realisation (binary32 state, bf16-split MFMA).
+struct DenseArgs {
+  const float* pos;        // [dim][cap], sorted
+  int64_t cap;
+  int32_t n;               // particles (one realisation)
+  const float* mass_in;    // [S_pad][cap]
+  float* mass_out;
+  float* q;                // written by the row-sum pass, read by the exchange
+  double* r;
+  float* bbox;             // [ceil(n / 32)][2 dim]
+  float escale;            // -log2(e) / sigma^2
+  float skip_s2;           // column tiles at squared distance > skip_s2 hold weights < 2^-40
+  __bf16* bparts;          // [3][16 ncb][cap]
+  int32_t ncb;             // column blocks of 16 (1 or 2)
+  int32_t S, react_a, react_b, norm;
+  double* audit_part;      // [ceil(n / 16)][S + 1]
+};
+constexpr int kDenseRowTile = 16;
+constexpr int kDenseColTile = 32;
+constexpr int64_t kDenseMaxN = (int64_t)1 << 17;
+// column blocks of 16 the contraction needs: [M_s, q M_s, q, 1] (symmetric) or [M_s, 1] (row)
+inline int dense_ncb(int S, int norm) { return ((norm == 0 ? 2 * S + 2 : S + 1) + 15) / 16; }
+hipError_t launch_dense_step(int dim, const DenseArgs& a, hipStream_t s);
+
 }  // namespace rwpt

@@ -396,3 +396,70 @@ def test_autotune_restores_state_and_keeps_parity(tmp_path, monkeypatch):
     assert rwpt.rwpt_get_tiling(e2.ctx) == (lanes, ref)
     assert (tmp_path / "tune.txt").read_text() == text
     e2.close()
+
+
+# ------------------------------------------------- full matrix on MFMA ----
+
+@pytest.mark.parametrize("dim,n,S,norm", [(1, 2000, 2, rwpt.RWPT_NORM_SYM), (1, 8192, 2, rwpt.RWPT_NORM_SYM),
+                                         (2, 3000, 2, rwpt.RWPT_NORM_SYM), (3, 2000, 8, rwpt.RWPT_NORM_SYM),
+                                         (2, 3000, 3, rwpt.RWPT_NORM_ROW), (1, 1000, 8, rwpt.RWPT_NORM_ROW),
+                                         (1, 77, 1, rwpt.RWPT_NORM_SYM)])
+def test_dense_full_matrix_matches_oracle(dim, n, S, norm):
+    D = {1: 1e-4, 2: 2e-3, 3: 1e-2}[dim]
+    dt, steps = 0.1, 5
+    x = f32(W.positions(n, dim, 500 + n))
+    M = f32(W.masses(n, S, 500 + n))
+    react = (0, 1) if S >= 2 else None
+    ens = rwpt.Ensemble(dim=dim, n_species=S, react=react, kappa=None, rw_ratio=0.0, precision=F32,
+                        norm=norm, path=rwpt.RWPT_PATH_DENSE, seed=3)
+    ens.init([n], x, M)
+    ens.step(dt, D, steps)
+    ref = oracle_run(x, M, D, dt, steps, math.inf, 32,
+                     norm=oracle.NORM_SYM if norm == rwpt.RWPT_NORM_SYM else oracle.NORM_ROW, react=react)
+    assert normerr(ens.masses(), ref) < 1e-5, normerr(ens.masses(), ref)
+    if norm == rwpt.RWPT_NORM_SYM:
+        # conserved by transfer and reaction: sum(A - B), or sum(M) without a reaction
+        a0 = oracle.audit(M, react)
+        a = ens.audit()[0]
+        k = S if react is not None else 0
+        assert abs(a[k] - a0[k]) <= 1e-6 * M[:2].sum()
+    ens.close()
+
+
+def test_dense_plain1d_n32768_two_steps_and_walk():
+    w = W.WORKLOADS["plain1d_n32768"]
+    x, M, sizes, _ = W.make_inputs(w)
+    x, M = f32(x), f32(M)
+    ens = rwpt.Ensemble(dim=1, n_species=2, kappa=None, rw_ratio=0.0, precision=F32,
+                        path=rwpt.RWPT_PATH_DENSE, seed=3)
+    ens.init(sizes, x, M)
+    ens.step(w.dt, w.D, 2)
+    ref = oracle_run(x, M, w.D, w.dt, 2, math.inf, 32)
+    assert normerr(ens.masses(), ref) < 1e-5
+    ens.close()
+    # with the walk, the transfer is checked on the positions the GPU stored
+    n = 6000
+    x = f32(W.positions(n, 2, 9))
+    M = f32(W.masses(n, 2, 9))
+    ens = rwpt.Ensemble(dim=2, n_species=2, kappa=None, rw_ratio=1.0, precision=F32,
+                        path=rwpt.RWPT_PATH_DENSE, seed=9)
+    ens.init([n], x, M)
+    ens.step(0.1, 1e-3, 1)
+    pos = ens.positions()
+    ref = oracle.transfer(pos, M, 1e-3, 0.1, kappa=math.inf, prec=32)
+    assert normerr(ens.masses(), ref) < 1e-5
+    ens.close()
+
+
+def test_dense_path_requires_full_matrix_binary32_single_realisation():
+    with pytest.raises(rwpt.RwptError) as ei:
+        rwpt.Ensemble(dim=1, kappa=3.0, path=rwpt.RWPT_PATH_DENSE)
+    assert ei.value.status == rwpt.RWPT_EINVAL
+    with pytest.raises(rwpt.RwptError) as ei:
+        rwpt.Ensemble(dim=1, kappa=None, precision=F64, path=rwpt.RWPT_PATH_DENSE)
+    assert ei.value.status == rwpt.RWPT_EUNSUPPORTED
+    ens = rwpt.Ensemble(dim=1, kappa=None, path=rwpt.RWPT_PATH_DENSE)
+    with pytest.raises(rwpt.RwptError) as ei:
+        ens.init([10, 10], W.positions(20, 1, 1), W.masses(20, 2, 1))
+    assert ei.value.status == rwpt.RWPT_EUNSUPPORTED
+    ens.close()
