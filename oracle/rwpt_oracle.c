@@ -41,9 +41,9 @@
  *   - cutoff predicate: a pair is a neighbour iff s^2 <= rc2 where
  *     rc2 = (kappa*kappa) * ((8*D)*dt) evaluated in binary64 and, for the
  *     binary32 predicate, rounded once to binary32; s^2 is evaluated in the
- *     predicate's precision as ((dx*dx) + (dy*dy)) + (dz*dz), each operation
- *     rounded, dimension order, no fused multiply-add.  kappa = +inf selects
- *     the full matrix (every pair).
+ *     predicate's precision as fma(dz, dz, fma(dy, dy, dx*dx)) with
+ *     dx = x_j - x_i, each operation correctly rounded, dimension order.
+ *     kappa = +inf selects the full matrix (every pair).
  *   - D = 0: the transfer is skipped (no mass moves).
  *   - reaction: m = max(0, min(A, B)); A -= m; B -= m.  This is the same
  *     update of (A, B) as the paper's conservative-component form
@@ -156,17 +156,17 @@ static double cutoff_rc2(double kappa, double D, double dt) {
   return kappa * kappa * sigma2;
 }
 
-/* s^2 in binary32, ((dx*dx) + (dy*dy)) + (dz*dz), every operation rounded.
- * volatile keeps the compiler from keeping wider intermediates. */
+/* s^2 in binary32: dx*dx rounded, then fma(dy, dy, .) and fma(dz, dz, .),
+ * each correctly rounded (C99 fmaf), dimension order.  volatile keeps the
+ * compiler from keeping wider intermediates. */
 static int within_f32(const double *xi, const double *xj, int d, float rc2f) {
   volatile float acc = 0.0f;
   for (int k = 0; k < d; ++k) {
     volatile float a = (float)xj[k];
     volatile float b = (float)xi[k];
     volatile float dx = a - b;
-    volatile float sq = dx * dx;
-    if (k == 0) acc = sq;
-    else acc = acc + sq;
+    if (k == 0) acc = dx * dx;
+    else acc = fmaf(dx, dx, acc);
   }
   return acc <= rc2f;
 }
@@ -175,9 +175,8 @@ static int within_f64(const double *xi, const double *xj, int d, double rc2) {
   volatile double acc = 0.0;
   for (int k = 0; k < d; ++k) {
     volatile double dx = xj[k] - xi[k];
-    volatile double sq = dx * dx;
-    if (k == 0) acc = sq;
-    else acc = acc + sq;
+    if (k == 0) acc = dx * dx;
+    else acc = fma(dx, dx, acc);
   }
   return acc <= rc2;
 }

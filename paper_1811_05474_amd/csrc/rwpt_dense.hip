@@ -50,11 +50,11 @@ __device__ __forceinline__ float sep2f(const float xi[DIM], const float xj[DIM])
   float s = d0 * d0;
   if constexpr (DIM > 1) {
     const float d1 = xj[1] - xi[1];
-    s = s + d1 * d1;
+    s = __builtin_fmaf(d1, d1, s);
   }
   if constexpr (DIM > 2) {
     const float d2 = xj[2] - xi[2];
-    s = s + d2 * d2;
+    s = __builtin_fmaf(d2, d2, s);
   }
   return s;
 }

@@ -89,9 +89,13 @@ __device__ __forceinline__ T reflect(T x, T lo, T hi) {
   return x;
 }
 
-// Squared separation used by the cutoff predicate: ((dx*dx) + (dy*dy)) + (dz*dz)
-// in the path's precision, every operation rounded (no contraction), so the
-// neighbour sets are reproducible bit for bit.
+// Squared separation used by the cutoff predicate: dx*dx, then
+// fma(dy, dy, .) and fma(dz, dz, .) in the path's precision, dx = x_j - x_i,
+// dimension order; every step is correctly rounded and nothing else is
+// contracted, so the neighbour sets are reproducible bit for bit.
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T, int DIM>
 __device__ __forceinline__ T sep2(const T xi[DIM], const T* __restrict__ pos, int64_t cap, uint32_t j) {
 #pragma clang fp contract(off)
@@ -99,11 +103,11 @@ __device__ __forceinline__ T sep2(const T xi[DIM], const T* __restrict__ pos, in
   T s = d0 * d0;
   if constexpr (DIM > 1) {
     const T d1 = pos[cap + j] - xi[1];
-    s = s + d1 * d1;
+    s = fma_t(d1, d1, s);
   }
   if constexpr (DIM > 2) {
     const T d2 = pos[2 * cap + j] - xi[2];
-    s = s + d2 * d2;
+    s = fma_t(d2, d2, s);
   }
   return s;
 }
@@ -115,11 +119,11 @@ __device__ __forceinline__ T sep2v(const T xi[DIM], const T xj[DIM]) {
   T s = d0 * d0;
   if constexpr (DIM > 1) {
     const T d1 = xj[1] - xi[1];
-    s = s + d1 * d1;
+    s = fma_t(d1, d1, s);
   }
   if constexpr (DIM > 2) {
     const T d2 = xj[2] - xi[2];
-    s = s + d2 * d2;
+    s = fma_t(d2, d2, s);
   }
   return s;
 }
@@ -128,6 +132,9 @@ __device__ __forceinline__ T sep2v(const T xi[DIM], const T xj[DIM]) {
 // together; with one lane per particle they are consecutive and uniform, so
 // they merge into wide scalar loads).
 constexpr int kUnroll = 4;
+// binary32 row partials are added into the binary64 accumulators at least
+// every kFlushBlocks * kUnroll candidates per lane
+constexpr uint32_t kFlushBlocks = 64;
 
 // Co-location weight exp(-s2 / sigma^2) (Eq. 3 without prefactor): binary32
 // uses the hardware exp2 with the scale -log2(e)/sigma^2; binary64 uses the
@@ -426,18 +433,24 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(
       T accr = (T)0;
       const uint32_t len = je - jb, nblk = len / (L * kUnroll);
       uint32_t j = jb + tl.gl;
-      for (uint32_t b = 0; b < nblk; ++b, j += L * kUnroll) {
-        T xj[kUnroll][DIM];
+      for (uint32_t b = 0; b < nblk;) {
+        // at most kFlushBlocks blocks per binary32 partial, then into binary64
+        const uint32_t bend = nblk - b > kFlushBlocks ? b + kFlushBlocks : nblk;
+        for (; b < bend; ++b, j += L * kUnroll) {
+          T xj[kUnroll][DIM];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
+          for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) xj[u][k] = pos[k * cap + j + u * L];
+            for (int k = 0; k < DIM; ++k) xj[u][k] = pos[k * cap + j + u * L];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const T s2 = sep2v<T, DIM>(xi, xj[u]);
-          const T w = kweight(s2, esc);
-          accr += (act && s2 <= rc2) ? w : (T)0;
+          for (int u = 0; u < kUnroll; ++u) {
+            const T s2 = sep2v<T, DIM>(xi, xj[u]);
+            const T w = kweight(s2, esc);
+            accr += (act && s2 <= rc2) ? w : (T)0;
+          }
         }
+        acc += (double)accr;
+        accr = (T)0;
       }
       for (; j < je; j += L) {
         const T s2 = sep2<T, DIM>(xi, pos, cap, j);
@@ -506,18 +519,26 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
 #pragma unroll
           for (int s = 0; s < SMAX; ++s) accr[s] += p * (mj[s] - Mi[s]);
         };
-        for (uint32_t b = 0; b < nblk; ++b, j += L * kUnroll) {
-          T xj[kUnroll][DIM], qj[kUnroll], mj[kUnroll][SMAX];
+        for (uint32_t b = 0; b < nblk;) {
+          const uint32_t bend = nblk - b > kFlushBlocks ? b + kFlushBlocks : nblk;
+          for (; b < bend; ++b, j += L * kUnroll) {
+            T xj[kUnroll][DIM], qj[kUnroll], mj[kUnroll][SMAX];
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kUnroll; ++u) {
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) xj[u][k] = pos[k * cap + j + u * L];
-            qj[u] = q[j + u * L];
+              for (int k = 0; k < DIM; ++k) xj[u][k] = pos[k * cap + j + u * L];
+              qj[u] = q[j + u * L];
 #pragma unroll
-            for (int s = 0; s < SMAX; ++s) mj[u][s] = min_[s * cap + j + u * L];
+              for (int s = 0; s < SMAX; ++s) mj[u][s] = min_[s * cap + j + u * L];
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) eval(xj[u], qj[u], mj[u]);
           }
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) eval(xj[u], qj[u], mj[u]);
+          for (int s = 0; s < SMAX; ++s) {
+            acc[s] += (double)accr[s];
+            accr[s] = (T)0;
+          }
         }
         for (; j < je; j += L) {
           T xj[DIM], mj[SMAX];
@@ -546,17 +567,27 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
 #pragma unroll
           for (int s = 0; s < SMAX; ++s) accr[s] += w * (mj[s] - Mi[s]);
         };
-        for (uint32_t b = 0; b < nblk; ++b, j += L * kUnroll) {
-          T xj[kUnroll][DIM], mj[kUnroll][SMAX];
+        for (uint32_t b = 0; b < nblk;) {
+          const uint32_t bend = nblk - b > kFlushBlocks ? b + kFlushBlocks : nblk;
+          for (; b < bend; ++b, j += L * kUnroll) {
+            T xj[kUnroll][DIM], mj[kUnroll][SMAX];
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
+            for (int u = 0; u < kUnroll; ++u) {
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) xj[u][k] = pos[k * cap + j + u * L];
+              for (int k = 0; k < DIM; ++k) xj[u][k] = pos[k * cap + j + u * L];
 #pragma unroll
-            for (int s = 0; s < SMAX; ++s) mj[u][s] = min_[s * cap + j + u * L];
+              for (int s = 0; s < SMAX; ++s) mj[u][s] = min_[s * cap + j + u * L];
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) eval(xj[u], mj[u]);
           }
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) eval(xj[u], mj[u]);
+          for (int s = 0; s < SMAX; ++s) {
+            acc[s] += (double)accr[s];
+            accr[s] = (T)0;
+          }
+          racc += (double)rr;
+          rr = (T)0;
         }
         for (; j < je; j += L) {
           T xj[DIM], mj[SMAX];
@@ -617,6 +648,312 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
     tot[SMAX] = va - vb;
   }
   // audit partials of this tile: lanes 0..G-1 hold the values
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+#pragma unroll
+    for (int s = 0; s <= SMAX; ++s) tot[s] += __shfl_xor(tot[s], off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    const int t = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    double* part = audit_part + (int64_t)t * (S + 1);
+    for (int s = 0; s < S; ++s) part[s] = tot[s < SMAX ? s : 0];
+    part[S] = tot[SMAX];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pair kernels, 4 lanes per particle with DPP row broadcast (binary32).
+//
+// A wave holds 16 particles (gi = lane & 15) in each of its four 16-lane rows
+// (gl = lane >> 4).  The tile's candidate rows are streamed as one virtual
+// list: every lane loads one candidate of a chunk of 64 (coalesced, one load
+// per array), then in 16 steps row gl evaluates candidate 16 gl + k, which
+// `row_share:k` broadcasts to the whole row straight into the consuming VALU
+// instruction.  Each particle sees all 64 candidates across its four lanes.
+// ---------------------------------------------------------------------------
+
+template <int K>
+__device__ __forceinline__ float rshare(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + K, 0xf,
+                                                               0xf, false));
+}
+
+template <int K, int N>
+struct Steps {
+  template <typename F>
+  __device__ __forceinline__ static void run(F&& f) {
+    f(std::integral_constant<int, K>{});
+    Steps<K + 1, N>::run(f);
+  }
+};
+template <int N>
+struct Steps<N, N> {
+  template <typename F>
+  __device__ __forceinline__ static void run(F&&) {}
+};
+
+// Wave-uniform cursor over the non-empty stencil rows of one segment.
+struct RowCursor {
+  int r;            // next stencil entry to examine
+  uint32_t jb, je;  // current row's sorted candidate range
+  uint32_t p;       // virtual index of jb
+  bool valid;
+};
+
+__device__ __forceinline__ void cursor_advance(RowCursor& c, const RealParams& P, const StencilRow* __restrict__ st,
+                                               const uint32_t* __restrict__ cell_start, int cy, int cz, int cxa,
+                                               int cxb) {
+  const int nc0 = P.nc[0], nc1 = P.nc[1], nc2 = P.nc[2];
+  c.valid = false;
+  while (c.r < P.n_stencil) {
+    const StencilRow sr = st[P.stencil_off + c.r];
+    ++c.r;
+    const int ny = cy + sr.dy, nz = cz + sr.dz;
+    if (ny < 0 || ny >= nc1 || nz < 0 || nz >= nc2) continue;
+    const int xa = cxa - sr.rx < 0 ? 0 : cxa - sr.rx;
+    const int xb = cxb + sr.rx > nc0 - 1 ? nc0 - 1 : cxb + sr.rx;
+    const int64_t cb = P.cell_off + ((int64_t)nz * nc1 + ny) * nc0;
+    const uint32_t jb = cell_start[cb + xa], je = cell_start[cb + xb + 1];
+    if (je > jb) {
+      c.jb = jb;
+      c.je = je;
+      c.valid = true;
+      return;
+    }
+  }
+}
+
+// Calls chunk(j, has) for every chunk of 64 virtual candidates of every
+// segment of the tile; `act` marks the lanes whose particle is in the segment.
+template <typename ChunkFn>
+__device__ __forceinline__ void for_tile_chunks(const RealParams& P, const StencilRow* __restrict__ st,
+                                                const uint32_t* __restrict__ cell_start, const TileLane& tl,
+                                                int32_t jdummy, ChunkFn&& chunk) {
+  const int lane = threadIdx.x & 63;
+  const int nc1 = P.nc[1];
+  int seg = 0;
+  while (seg < tl.n_in) {
+    const int seg_row = __builtin_amdgcn_readlane(tl.row, seg);
+    const unsigned long long m =
+        __ballot(tl.gl == 0 && tl.gi > seg && (tl.gi >= tl.n_in || tl.row != seg_row));
+    int seg_end = m ? (__ffsll((unsigned long long)m) - 1) : tl.n_in;
+    seg_end = seg_end > tl.n_in ? tl.n_in : seg_end;
+    const int cxa = __builtin_amdgcn_readlane(tl.cx, seg);
+    const int cxb = __builtin_amdgcn_readlane(tl.cx, seg_end - 1);
+    const bool act = tl.valid && tl.gi >= seg && tl.gi < seg_end;
+    const int cy = seg_row % nc1, cz = seg_row / nc1;
+    RowCursor c;
+    c.r = 0;
+    c.p = 0;
+    cursor_advance(c, P, st, cell_start, cy, cz, cxa, cxb);
+    uint32_t vbase = 0;
+    bool more = c.valid;
+    while (more) {
+      const uint32_t v = vbase + (uint32_t)lane;
+      int32_t j = jdummy;
+      bool has = false;
+      while (c.valid) {
+        const uint32_t len = c.je - c.jb;
+        if (v >= c.p && v < c.p + len) {
+          j = (int32_t)(c.jb + (v - c.p));
+          has = true;
+        }
+        if (c.p + len <= vbase + 64) {
+          c.p += len;
+          cursor_advance(c, P, st, cell_start, cy, cz, cxa, cxb);
+        } else {
+          break;
+        }
+      }
+      chunk(j, has, act);
+      more = c.valid;
+      vbase += 64;
+    }
+    seg = seg_end;
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
+    const float* __restrict__ pos, const int64_t cap, const uint32_t* __restrict__ skey,
+    const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles, const int32_t ntiles,
+    const RealParams* __restrict__ rp, const StencilRow* __restrict__ st, double* __restrict__ r_out,
+    float* __restrict__ q_out) {
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<2>(tiles, ntiles, tl, tile)) return;
+  const RealParams& P = rp[tile.real];
+  const int32_t ii = tl.valid ? tl.i : tile.end - 1;
+  float xi[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  lane_cell<float, DIM>(P, skey, ii, tl);
+  const float rc2 = P.rc2_f, esc = P.escale_f;
+  double acc = 0.0;
+  if (P.active) {
+    for_tile_chunks(P, st, cell_start, tl, tile.begin, [&](int32_t j, bool has, bool act) {
+      float xj[DIM];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) xj[k] = pos[k * cap + j];
+      if (!has) xj[0] = 3.0e38f;  // s^2 overflows to +inf: outside the cutoff, weight 0
+      float a = 0.0f;
+      Steps<0, 16>::run([&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        const float d0 = rshare<K>(xj[0]) - xi[0];
+        float s2 = d0 * d0;
+        if constexpr (DIM > 1) {
+          const float d1 = rshare<K>(xj[1]) - xi[1];
+          s2 = __builtin_fmaf(d1, d1, s2);
+        }
+        if constexpr (DIM > 2) {
+          const float d2 = rshare<K>(xj[2]) - xi[2];
+          s2 = __builtin_fmaf(d2, d2, s2);
+        }
+        const float w = kweight(s2, esc);
+        a += (act && s2 <= rc2) ? w : 0.0f;
+      });
+      acc += (double)a;
+    });
+  } else {
+    acc = 1.0;
+  }
+  acc += __shfl_xor(acc, 16);
+  acc += __shfl_xor(acc, 32);
+  if (tl.gl == 0 && tl.valid) {
+    if (!P.active) acc = 1.0;
+    r_out[tl.i] = acc;
+    q_out[tl.i] = (float)(1.0 / acc);
+  }
+}
+
+template <int DIM, int SMAX>
+__global__ __launch_bounds__(kBlock) void k_exchange_dpp(
+    const float* __restrict__ pos, const int64_t cap, const float* __restrict__ min_, float* __restrict__ mout,
+    const float* __restrict__ q, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ cell_start,
+    const Tile* __restrict__ tiles, const int32_t ntiles, const RealParams* __restrict__ rp,
+    const StencilRow* __restrict__ st, const int32_t S, const int32_t react_a, const int32_t react_b,
+    const int32_t norm, double* __restrict__ audit_part) {
+  constexpr int G = 16;
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<2>(tiles, ntiles, tl, tile)) return;
+  const RealParams& P = rp[tile.real];
+  const int32_t ii = tl.valid ? tl.i : tile.end - 1;
+  float xi[DIM];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  float Mi[SMAX];
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) Mi[s] = min_[s * cap + ii];
+  lane_cell<float, DIM>(P, skey, ii, tl);
+  const float rc2 = P.rc2_f, esc = P.escale_f;
+  double acc[SMAX];
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) acc[s] = 0.0;
+  double racc = 0.0;
+  const bool sym = (norm == 0);
+  const float qi = q[ii];
+  if (P.active) {
+    for_tile_chunks(P, st, cell_start, tl, tile.begin, [&](int32_t j, bool has, bool act) {
+      float xj[DIM], mj[SMAX];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) xj[k] = pos[k * cap + j];
+      if (!has) xj[0] = 3.0e38f;  // outside the cutoff, weight 0
+      const float qj = q[j];
+      // species rows S..SMAX-1 exist and hold zeros, so no guard is needed
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) mj[s] = min_[s * cap + j];
+      float accr[SMAX];
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) accr[s] = 0.0f;
+      float rr = 0.0f;
+      if (sym) {
+        Steps<0, 16>::run([&](auto kc) {
+          constexpr int K = decltype(kc)::value;
+          const float d0 = rshare<K>(xj[0]) - xi[0];
+          float s2 = d0 * d0;
+          if constexpr (DIM > 1) {
+            const float d1 = rshare<K>(xj[1]) - xi[1];
+            s2 = __builtin_fmaf(d1, d1, s2);
+          }
+          if constexpr (DIM > 2) {
+            const float d2 = rshare<K>(xj[2]) - xi[2];
+            s2 = __builtin_fmaf(d2, d2, s2);
+          }
+          float w = kweight(s2, esc);
+          w = (act && s2 <= rc2) ? w : 0.0f;
+          const float p = w * (rshare<K>(qj) + qi);  // 2 * symmetric P_ij
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s) accr[s] += p * (rshare<K>(mj[s]) - Mi[s]);
+        });
+      } else {
+        Steps<0, 16>::run([&](auto kc) {
+          constexpr int K = decltype(kc)::value;
+          const float d0 = rshare<K>(xj[0]) - xi[0];
+          float s2 = d0 * d0;
+          if constexpr (DIM > 1) {
+            const float d1 = rshare<K>(xj[1]) - xi[1];
+            s2 = __builtin_fmaf(d1, d1, s2);
+          }
+          if constexpr (DIM > 2) {
+            const float d2 = rshare<K>(xj[2]) - xi[2];
+            s2 = __builtin_fmaf(d2, d2, s2);
+          }
+          float w = kweight(s2, esc);
+          w = (act && s2 <= rc2) ? w : 0.0f;
+          rr += w;
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s) accr[s] += w * (rshare<K>(mj[s]) - Mi[s]);
+        });
+      }
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
+      racc += (double)rr;
+    });
+  }
+#pragma unroll
+  for (int off = 16; off < 64; off <<= 1) {
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) acc[s] += __shfl_xor(acc[s], off);
+    racc += __shfl_xor(racc, off);
+  }
+  double tot[SMAX + 1];
+#pragma unroll
+  for (int s = 0; s <= SMAX; ++s) tot[s] = 0.0;
+  if (tl.gl == 0 && tl.valid) {
+    double Mn[SMAX];
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      double dm = 0.0;
+      if (P.active) dm = sym ? 0.25 * acc[s] : 0.5 * acc[s] / racc;
+      Mn[s] = (double)Mi[s] + dm;
+    }
+    if (react_a >= 0) {
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s)
+        if (s == react_a) {
+#pragma unroll
+          for (int t2 = 0; t2 < SMAX; ++t2)
+            if (t2 == react_b) {
+              double m = Mn[s] < Mn[t2] ? Mn[s] : Mn[t2];
+              m = m > 0.0 ? m : 0.0;
+              Mn[s] -= m;
+              Mn[t2] -= m;
+            }
+        }
+    }
+    double va = 0.0, vb = 0.0;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s)
+      if (s < S) {
+        const float v = (float)Mn[s];
+        mout[s * cap + tl.i] = v;
+        tot[s] = (double)v;
+        if (s == react_a) va = (double)v;
+        if (s == react_b) vb = (double)v;
+      }
+    tot[SMAX] = va - vb;
+  }
 #pragma unroll
   for (int off = 1; off < G; off <<= 1) {
 #pragma unroll
@@ -892,6 +1229,17 @@ static hipError_t dispatch_tdl(int fp64, int dim, int log2l, F&& f) {
 hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
+  if (!fp64 && log2l == 2) {
+    auto go = [&](auto d) {
+      hipLaunchKernelGGL((k_rowsum_dpp<decltype(d)::value>), g, b, 0, s, (const float*)a.pos, a.cap, a.skey,
+                         a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (float*)a.q_out);
+    };
+    if (dim == 1) go(IC<1>{});
+    else if (dim == 2) go(IC<2>{});
+    else if (dim == 3) go(IC<3>{});
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
     using T = decltype(t);
     hipLaunchKernelGGL((k_rowsum<T, decltype(d)::value, decltype(l)::value>), g, b, 0, s, (const T*)a.pos,
@@ -903,6 +1251,23 @@ hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipS
   if (a.ntiles <= 0) return hipSuccess;
   if (a.S < 1 || a.S > 8) return hipErrorInvalidValue;
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
+  if (!fp64 && log2l == 2) {
+    auto go = [&](auto d) {
+      constexpr int D = decltype(d)::value;
+#define RWPT_EXD_ARGS                                                                                  \
+  (const float*)a.pos, a.cap, (const float*)a.mass_in, (float*)a.mass_out, (const float*)a.q_in, a.skey, \
+      a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.S, a.react_a, a.react_b, a.norm, a.audit_part
+      if (a.S <= 2) hipLaunchKernelGGL((k_exchange_dpp<D, 2>), g, b, 0, s, RWPT_EXD_ARGS);
+      else if (a.S <= 4) hipLaunchKernelGGL((k_exchange_dpp<D, 4>), g, b, 0, s, RWPT_EXD_ARGS);
+      else hipLaunchKernelGGL((k_exchange_dpp<D, 8>), g, b, 0, s, RWPT_EXD_ARGS);
+#undef RWPT_EXD_ARGS
+    };
+    if (dim == 1) go(IC<1>{});
+    else if (dim == 2) go(IC<2>{});
+    else if (dim == 3) go(IC<3>{});
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
   return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
     using T = decltype(t);
     constexpr int D = decltype(d)::value, L = decltype(l)::value;
