@@ -152,7 +152,7 @@ static void default_refine(int dim, double out[3]) {
   if (dim == 1) {
     out[0] = 16.0; out[1] = 1.0; out[2] = 1.0;
   } else if (dim == 2) {
-    out[0] = 8.0; out[1] = 3.0; out[2] = 1.0;
+    out[0] = 16.0; out[1] = 2.0; out[2] = 1.0;
   } else {
     out[0] = 4.0; out[1] = 1.0; out[2] = 1.0;
   }
@@ -164,7 +164,8 @@ static void default_refine(int dim, double out[3]) {
 static int default_lanes(int dim, int64_t n) {
   if (dim == 1) return 16;
   if (dim == 3) return 4;
-  return n >= (int64_t)1 << 19 ? 4 : 8;
+  // 4 lanes per particle uses the row-broadcast (DPP) kernels in binary32
+  return n >= (int64_t)1 << 18 ? 4 : 8;
 }
 
 static void invalidate_graphs(rwpt_ctx* c) {
