@@ -85,8 +85,10 @@ typedef struct rwpt_config {
   int32_t precision;      /* RWPT_FP32 or RWPT_FP64 */
   int32_t norm;           /* RWPT_NORM_SYM or RWPT_NORM_ROW */
   int32_t path;           /* RWPT_PATH_* */
-  int32_t tile_lanes;     /* lanes sharing one particle in the pair kernels: 1, 4, 8 or 16;
-                             0 = choose from dim */
+  int32_t tile_lanes;     /* lanes sharing one particle in the pair kernels, which then
+                             share one candidate list per tile: 1, 4, 8 or 16;
+                             -1 = one lane per particle with its own candidate rows
+                             (sparse neighbourhoods); 0 = choose from dim and N */
   double cell_refine[3];  /* cells per cutoff length along each axis (> 0); 0 = choose */
   int32_t device;         /* HIP device ordinal */
   int32_t use_graph;      /* 1 = replay each rwpt_step as one captured HIP graph */

@@ -138,11 +138,12 @@ static rwpt_status fail(rwpt_ctx* c, rwpt_status st, const char* fmt, ...) {
 
 static int lanes_to_log2(int lanes) {
   switch (lanes) {
+    case -1: return kPrivateLists;
     case 1: return 0;
     case 4: return 2;
     case 8: return 3;
     case 16: return 4;
-    default: return -1;
+    default: return -2;  // invalid
   }
 }
 
@@ -154,7 +155,7 @@ static void default_refine(int dim, double out[3]) {
   } else if (dim == 2) {
     out[0] = 16.0; out[1] = 2.0; out[2] = 1.0;
   } else {
-    out[0] = 4.0; out[1] = 1.0; out[2] = 1.0;
+    out[0] = 2.0; out[1] = 1.0; out[2] = 1.0;
   }
 }
 
@@ -163,7 +164,7 @@ static void default_refine(int dim, double out[3]) {
 // candidate unions per lane) otherwise.
 static int default_lanes(int dim, int64_t n) {
   if (dim == 1) return 16;
-  if (dim == 3) return 4;
+  if (dim == 3) return -1;  // sparse neighbourhoods: private candidate rows
   // 4 lanes per particle uses the row-broadcast (DPP) kernels in binary32
   return n >= (int64_t)1 << 18 ? 4 : 8;
 }
@@ -264,7 +265,7 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   double defr[3];
   default_refine(dim, defr);
   for (int k = 0; k < 3; ++k) c->refine[k] = cfg.cell_refine[k] > 0 ? cfg.cell_refine[k] : defr[k];
-  const int G = 64 >> c->log2l;
+  const int G = c->log2l == kPrivateLists ? 64 : 64 >> c->log2l;
 
   c->h_rp.assign(c->n_real, RealParams{});
   c->h_st.clear();
@@ -600,8 +601,8 @@ rwpt_status rwpt_create(const rwpt_config* cfg, rwpt_ctx** out) {
     return fail(nullptr, RWPT_EINVAL, "the dense path evaluates every pair: kappa must be INFINITY");
   if (c.path == RWPT_PATH_DENSE && c.precision != RWPT_FP32)
     return fail(nullptr, RWPT_EUNSUPPORTED, "the dense (matrix-core) path is binary32 only");
-  if (c.tile_lanes != 0 && lanes_to_log2(c.tile_lanes) < 0)
-    return fail(nullptr, RWPT_EINVAL, "tile_lanes must be 0, 1, 4, 8 or 16 (got %d)", c.tile_lanes);
+  if (c.tile_lanes != 0 && lanes_to_log2(c.tile_lanes) == -2)
+    return fail(nullptr, RWPT_EINVAL, "tile_lanes must be -1, 0, 1, 4, 8 or 16 (got %d)", c.tile_lanes);
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(c.cell_refine[k]) || c.cell_refine[k] < 0.0 || c.cell_refine[k] > 64.0)
       return fail(nullptr, RWPT_EINVAL, "cell_refine[%d] must be in [0, 64]", k);
@@ -1024,7 +1025,7 @@ static std::vector<std::pair<int, std::array<double, 3>>> tuning_candidates(int 
   else if (dim == 2) refs = {{8, 1, 1}, {16, 1, 1}, {4, 2, 1}, {8, 2, 1}, {8, 3, 1}, {16, 3, 1}, {8, 4, 1}};
   else refs = {{2, 1, 1}, {4, 1, 1}, {8, 1, 1}, {4, 2, 2}, {8, 0.5, 0.5}, {16, 0.5, 0.5}};
   std::vector<std::pair<int, std::array<double, 3>>> out;
-  for (int lanes : {1, 4, 8, 16})
+  for (int lanes : {-1, 1, 4, 8, 16})
     for (auto& r : refs) out.push_back({lanes, r});
   return out;
 }
@@ -1051,7 +1052,7 @@ static bool tuning_cache_lookup(const std::string& key, int* lanes, double ref[3
     if (key == line) {
       int l;
       double r0, r1, r2;
-      if (sscanf(bar + 1, "%d %lf %lf %lf", &l, &r0, &r1, &r2) == 4 && lanes_to_log2(l) >= 0) {
+      if (sscanf(bar + 1, "%d %lf %lf %lf", &l, &r0, &r1, &r2) == 4 && lanes_to_log2(l) != -2) {
         *lanes = l;
         ref[0] = r0;
         ref[1] = r1;

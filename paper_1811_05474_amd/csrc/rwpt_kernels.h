@@ -53,7 +53,10 @@ hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
 // so rows S..padded_species(S)-1 are allocated and kept at zero.
 inline int padded_species(int S) { return S <= 2 ? 2 : (S <= 4 ? 4 : 8); }
 
-// Pair kernels (one wave per tile).  log2l: lanes per particle = 1 << log2l.
+// Pair kernels (one wave per tile).  log2l: lanes per particle = 1 << log2l,
+// or kPrivateLists: one lane per particle with its own candidate rows (tiles
+// of 64 particles).
+constexpr int kPrivateLists = -1;
 hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);

@@ -407,6 +407,64 @@ __device__ __forceinline__ void lane_cell(const RealParams& P, const uint32_t* _
   tl.row = (int)(lk / (uint32_t)P.nc[0]);
 }
 
+// After the lane reductions: new masses (Eq. 6), reaction, and the tile's
+// audit partials.  `writer` lanes (one per particle) hold acc / racc; lanes
+// 0..G-1 are the writers' first copies, so the audit is reduced over them.
+template <typename T, int SMAX, int G>
+__device__ __forceinline__ void exchange_epilogue(const RealParams& P, bool sym, const double acc[SMAX],
+                                                  double racc, const T Mi[SMAX], bool writer, int32_t i,
+                                                  T* __restrict__ mout, int64_t cap, int S, int react_a,
+                                                  int react_b, double* __restrict__ audit_part) {
+  double tot[SMAX + 1];
+#pragma unroll
+  for (int s = 0; s <= SMAX; ++s) tot[s] = 0.0;
+  if (writer) {
+    double Mn[SMAX];
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s) {
+      double dm = 0.0;
+      if (P.active) dm = sym ? 0.25 * acc[s] : 0.5 * acc[s] / racc;
+      Mn[s] = (double)Mi[s] + dm;
+    }
+    if (react_a >= 0) {
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s)
+        if (s == react_a) {
+#pragma unroll
+          for (int t2 = 0; t2 < SMAX; ++t2)
+            if (t2 == react_b) {
+              double m = Mn[s] < Mn[t2] ? Mn[s] : Mn[t2];
+              m = m > 0.0 ? m : 0.0;
+              Mn[s] -= m;
+              Mn[t2] -= m;
+            }
+        }
+    }
+    double va = 0.0, vb = 0.0;
+#pragma unroll
+    for (int s = 0; s < SMAX; ++s)
+      if (s < S) {
+        const T v = (T)Mn[s];
+        mout[s * cap + i] = v;
+        tot[s] = (double)v;
+        if (s == react_a) va = (double)v;
+        if (s == react_b) vb = (double)v;
+      }
+    tot[SMAX] = va - vb;
+  }
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+#pragma unroll
+    for (int s = 0; s <= SMAX; ++s) tot[s] += __shfl_xor(tot[s], off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    const int t = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    double* part = audit_part + (int64_t)t * (S + 1);
+    for (int s = 0; s < S; ++s) part[s] = tot[s < SMAX ? s : 0];
+    part[S] = tot[SMAX];
+  }
+}
+
 // Row sums r_i = sum_{j in N(i)} w_ij (self included) and q_i = 1 / r_i:
 // the normalisation of the co-location weights.
 template <typename T, int DIM, int LOG2L>
@@ -609,56 +667,8 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
     for (int s = 0; s < SMAX; ++s) acc[s] += __shfl_xor(acc[s], off);
     racc += __shfl_xor(racc, off);
   }
-  // New masses (Eq. 6), reaction, audit contributions.
-  double tot[SMAX + 1];
-#pragma unroll
-  for (int s = 0; s <= SMAX; ++s) tot[s] = 0.0;
-  if (tl.gl == 0 && tl.valid) {
-    double Mn[SMAX];
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      double dm = 0.0;
-      if (P.active) dm = sym ? 0.25 * acc[s] : 0.5 * acc[s] / racc;
-      Mn[s] = (double)Mi[s] + dm;
-    }
-    if (react_a >= 0) {
-#pragma unroll
-      for (int s = 0; s < SMAX; ++s)
-        if (s == react_a) {
-#pragma unroll
-          for (int t2 = 0; t2 < SMAX; ++t2)
-            if (t2 == react_b) {
-              double m = Mn[s] < Mn[t2] ? Mn[s] : Mn[t2];
-              m = m > 0.0 ? m : 0.0;
-              Mn[s] -= m;
-              Mn[t2] -= m;
-            }
-        }
-    }
-    double va = 0.0, vb = 0.0;
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s)
-      if (s < S) {
-        const T v = (T)Mn[s];
-        mout[s * cap + tl.i] = v;
-        tot[s] = (double)v;
-        if (s == react_a) va = (double)v;
-        if (s == react_b) vb = (double)v;
-      }
-    tot[SMAX] = va - vb;
-  }
-  // audit partials of this tile: lanes 0..G-1 hold the values
-#pragma unroll
-  for (int off = 1; off < G; off <<= 1) {
-#pragma unroll
-    for (int s = 0; s <= SMAX; ++s) tot[s] += __shfl_xor(tot[s], off);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
-    double* part = audit_part + (int64_t)t * (S + 1);
-    for (int s = 0; s < S; ++s) part[s] = tot[s < SMAX ? s : 0];
-    part[S] = tot[SMAX];
-  }
+  exchange_epilogue<T, SMAX, G>(P, sym, acc, racc, Mi, tl.gl == 0 && tl.valid, tl.i, mout, cap, S, react_a,
+                                react_b, audit_part);
 }
 
 // ---------------------------------------------------------------------------
@@ -917,54 +927,115 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
     for (int s = 0; s < SMAX; ++s) acc[s] += __shfl_xor(acc[s], off);
     racc += __shfl_xor(racc, off);
   }
-  double tot[SMAX + 1];
+  exchange_epilogue<float, SMAX, G>(P, sym, acc, racc, Mi, tl.gl == 0 && tl.valid, tl.i, mout, cap, S,
+                                    react_a, react_b, audit_part);
+}
+
+// ---------------------------------------------------------------------------
+// Pair kernels with private candidate lists: one lane per particle, each lane
+// walks its own stencil rows [cx - rx, cx + rx] around its own cell.  Suited
+// to sparse neighbourhoods, where the candidate union of a shared tile would
+// be mostly misses.
+// ---------------------------------------------------------------------------
+
+template <typename T, int DIM, typename RowFn>
+__device__ __forceinline__ void for_own_rows(const RealParams& P, const StencilRow* __restrict__ st,
+                                             const uint32_t* __restrict__ cell_start, uint32_t lk, RowFn&& fn) {
+  const int nc0 = P.nc[0], nc1 = P.nc[1], nc2 = P.nc[2];
+  const int cx = (int)(lk % (uint32_t)nc0);
+  const int rest = (int)(lk / (uint32_t)nc0);
+  const int cy = rest % nc1, cz = rest / nc1;
+  for (int r = 0; r < P.n_stencil; ++r) {
+    const StencilRow sr = st[P.stencil_off + r];
+    const int ny = cy + sr.dy, nz = cz + sr.dz;
+    if (ny < 0 || ny >= nc1 || nz < 0 || nz >= nc2) continue;
+    const int xa = cx - sr.rx < 0 ? 0 : cx - sr.rx;
+    const int xb = cx + sr.rx > nc0 - 1 ? nc0 - 1 : cx + sr.rx;
+    const int64_t cb = P.cell_off + ((int64_t)nz * nc1 + ny) * nc0;
+    fn(cell_start[cb + xa], cell_start[cb + xb + 1]);
+  }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_rowsum_priv(
+    const T* __restrict__ pos, const int64_t cap, const uint32_t* __restrict__ skey,
+    const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles, const int32_t ntiles,
+    const RealParams* __restrict__ rp, const StencilRow* __restrict__ st, double* __restrict__ r_out,
+    T* __restrict__ q_out) {
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<0>(tiles, ntiles, tl, tile)) return;
+  const RealParams& P = rp[tile.real];
+  if (!tl.valid) return;
+  T xi[DIM];
 #pragma unroll
-  for (int s = 0; s <= SMAX; ++s) tot[s] = 0.0;
-  if (tl.gl == 0 && tl.valid) {
-    double Mn[SMAX];
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s) {
-      double dm = 0.0;
-      if (P.active) dm = sym ? 0.25 * acc[s] : 0.5 * acc[s] / racc;
-      Mn[s] = (double)Mi[s] + dm;
-    }
-    if (react_a >= 0) {
-#pragma unroll
-      for (int s = 0; s < SMAX; ++s)
-        if (s == react_a) {
-#pragma unroll
-          for (int t2 = 0; t2 < SMAX; ++t2)
-            if (t2 == react_b) {
-              double m = Mn[s] < Mn[t2] ? Mn[s] : Mn[t2];
-              m = m > 0.0 ? m : 0.0;
-              Mn[s] -= m;
-              Mn[t2] -= m;
-            }
-        }
-    }
-    double va = 0.0, vb = 0.0;
-#pragma unroll
-    for (int s = 0; s < SMAX; ++s)
-      if (s < S) {
-        const float v = (float)Mn[s];
-        mout[s * cap + tl.i] = v;
-        tot[s] = (double)v;
-        if (s == react_a) va = (double)v;
-        if (s == react_b) vb = (double)v;
+  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + tl.i];
+  const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
+  double acc = 1.0;  // only the self weight when the transfer is off
+  if (P.active) {
+    acc = 0.0;
+    for_own_rows<T, DIM>(P, st, cell_start, skey[tl.i] - (uint32_t)P.cell_off, [&](uint32_t jb, uint32_t je) {
+      T a = (T)0;
+      for (uint32_t j = jb; j < je; ++j) {
+        const T s2 = sep2<T, DIM>(xi, pos, cap, j);
+        const T w = kweight(s2, esc);
+        a += s2 <= rc2 ? w : (T)0;
       }
-    tot[SMAX] = va - vb;
+      acc += (double)a;
+    });
   }
+  r_out[tl.i] = acc;
+  q_out[tl.i] = (T)(1.0 / acc);
+}
+
+template <typename T, int DIM, int SMAX>
+__global__ __launch_bounds__(kBlock) void k_exchange_priv(
+    const T* __restrict__ pos, const int64_t cap, const T* __restrict__ min_, T* __restrict__ mout,
+    const T* __restrict__ q, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ cell_start,
+    const Tile* __restrict__ tiles, const int32_t ntiles, const RealParams* __restrict__ rp,
+    const StencilRow* __restrict__ st, const int32_t S, const int32_t react_a, const int32_t react_b,
+    const int32_t norm, double* __restrict__ audit_part) {
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<0>(tiles, ntiles, tl, tile)) return;
+  const RealParams& P = rp[tile.real];
+  const int32_t ii = tl.valid ? tl.i : tile.end - 1;
+  T xi[DIM];
 #pragma unroll
-  for (int off = 1; off < G; off <<= 1) {
+  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  T Mi[SMAX];
 #pragma unroll
-    for (int s = 0; s <= SMAX; ++s) tot[s] += __shfl_xor(tot[s], off);
+  for (int s = 0; s < SMAX; ++s) Mi[s] = min_[s * cap + ii];
+  const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
+  double acc[SMAX];
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) acc[s] = 0.0;
+  double racc = 0.0;
+  const bool sym = (norm == 0);
+  if (P.active && tl.valid) {
+    const T qi = q[ii];
+    for_own_rows<T, DIM>(P, st, cell_start, skey[ii] - (uint32_t)P.cell_off, [&](uint32_t jb, uint32_t je) {
+      T accr[SMAX];
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) accr[s] = (T)0;
+      T rr = (T)0;
+      for (uint32_t j = jb; j < je; ++j) {
+        const T s2 = sep2<T, DIM>(xi, pos, cap, j);
+        if (!(s2 <= rc2)) continue;  // sparse: most candidates miss, skip their loads
+        const T w = kweight(s2, esc);
+        // species rows S..SMAX-1 exist and hold zeros
+        const T p = sym ? w * (qi + q[j]) : w;
+        rr += w;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) accr[s] += p * (min_[s * cap + j] - Mi[s]);
+      }
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
+      racc += (double)rr;
+    });
   }
-  if ((threadIdx.x & 63) == 0) {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
-    double* part = audit_part + (int64_t)t * (S + 1);
-    for (int s = 0; s < S; ++s) part[s] = tot[s < SMAX ? s : 0];
-    part[S] = tot[SMAX];
-  }
+  exchange_epilogue<T, SMAX, 64>(P, sym, acc, racc, Mi, tl.valid, tl.i, mout, cap, S, react_a, react_b,
+                                 audit_part);
 }
 
 // Counts ordered pairs j != i within the cutoff and candidate evaluations.
@@ -1229,6 +1300,13 @@ static hipError_t dispatch_tdl(int fp64, int dim, int log2l, F&& f) {
 hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
+  if (log2l == kPrivateLists) {
+    return dispatch_tdl(fp64, dim, 0, [&](auto t, auto d, auto) {
+      using T = decltype(t);
+      hipLaunchKernelGGL((k_rowsum_priv<T, decltype(d)::value>), g, b, 0, s, (const T*)a.pos, a.cap, a.skey,
+                         a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (T*)a.q_out);
+    });
+  }
   if (!fp64 && log2l == 2) {
     auto go = [&](auto d) {
       hipLaunchKernelGGL((k_rowsum_dpp<decltype(d)::value>), g, b, 0, s, (const float*)a.pos, a.cap, a.skey,
@@ -1251,6 +1329,19 @@ hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipS
   if (a.ntiles <= 0) return hipSuccess;
   if (a.S < 1 || a.S > 8) return hipErrorInvalidValue;
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
+  if (log2l == kPrivateLists) {
+    return dispatch_tdl(fp64, dim, 0, [&](auto t, auto d, auto) {
+      using T = decltype(t);
+      constexpr int D = decltype(d)::value;
+#define RWPT_EXP_ARGS                                                                                  \
+  (const T*)a.pos, a.cap, (const T*)a.mass_in, (T*)a.mass_out, (const T*)a.q_in, a.skey, a.cell_start,   \
+      a.tiles, a.ntiles, a.rp, a.st, a.S, a.react_a, a.react_b, a.norm, a.audit_part
+      if (a.S <= 2) hipLaunchKernelGGL((k_exchange_priv<T, D, 2>), g, b, 0, s, RWPT_EXP_ARGS);
+      else if (a.S <= 4) hipLaunchKernelGGL((k_exchange_priv<T, D, 4>), g, b, 0, s, RWPT_EXP_ARGS);
+      else hipLaunchKernelGGL((k_exchange_priv<T, D, 8>), g, b, 0, s, RWPT_EXP_ARGS);
+#undef RWPT_EXP_ARGS
+    });
+  }
   if (!fp64 && log2l == 2) {
     auto go = [&](auto d) {
       constexpr int D = decltype(d)::value;
@@ -1283,6 +1374,7 @@ hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipS
 
 hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
+  if (log2l == kPrivateLists) log2l = 0;  // same tiles of 64
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
   return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
     using T = decltype(t);
@@ -1292,6 +1384,7 @@ hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStre
 
 hipError_t launch_nbr_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
+  if (log2l == kPrivateLists) log2l = 0;  // same tiles of 64
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
   return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
     using T = decltype(t);
@@ -1301,6 +1394,7 @@ hipError_t launch_nbr_count(int fp64, int dim, int log2l, const PairArgs& a, hip
 
 hipError_t launch_nbr_fill(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
+  if (log2l == kPrivateLists) log2l = 0;  // same tiles of 64
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
   return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
     using T = decltype(t);

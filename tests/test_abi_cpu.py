@@ -48,7 +48,7 @@ def test_config_struct_matches_c_layout(lib):
 @pytest.mark.parametrize("field,value", [
     ("dim", 0), ("dim", 4), ("n_species", 0), ("n_species", 9), ("react_a", 5), ("kappa", 0.0),
     ("kappa", -1.0), ("kappa", float("nan")), ("rw_ratio", -1.0), ("precision", 2), ("norm", 3),
-    ("path", 7), ("tile_lanes", 3), ("tile_lanes", 32), ("device", -1), ("use_graph", 2),
+    ("path", 7), ("tile_lanes", 3), ("tile_lanes", 32), ("tile_lanes", -2), ("device", -1), ("use_graph", 2),
 ])
 def test_create_rejects_bad_config(lib, field, value):
     cfg = rwpt.rwpt_config_default()

@@ -114,7 +114,7 @@ def test_neighbor_lists_bit_exact_1d():
 # ------------------------------------------------------------------ 2-D ----
 
 @pytest.mark.parametrize("prec", [F32, F64])
-@pytest.mark.parametrize("lanes", [1, 4, 8, 16])
+@pytest.mark.parametrize("lanes", [-1, 1, 4, 8, 16])
 def test_neighbor_lists_bit_exact_2d(prec, lanes):
     n, D, dt = 40000, 2e-4, 0.1  # about the neighbour count of the 10^6-particle case
     x = f32(W.positions(n, 2, 321))
@@ -132,7 +132,7 @@ def test_neighbor_lists_bit_exact_2d(prec, lanes):
 
 
 @pytest.mark.parametrize("prec,tol", [(F32, 1e-5), (F64, 1e-12)])
-@pytest.mark.parametrize("lanes", [0, 1, 4, 8, 16])
+@pytest.mark.parametrize("lanes", [0, -1, 1, 4, 8, 16])
 def test_walk2d_step_with_walk_replayed(prec, tol, lanes):
     n, D, dt, seed = 30000, 2e-4, 0.1, 99
     x = W.positions(n, 2, seed)
@@ -238,13 +238,14 @@ def test_batch_with_empty_and_single_realisations():
 # --------------------------------------------------------------------- 3-D ----
 
 @pytest.mark.parametrize("prec,tol", [(F32, 1e-5), (F64, 1e-12)])
-def test_walk3d_eight_species(prec, tol):
+@pytest.mark.parametrize("lanes", [0, -1, 4])
+def test_walk3d_eight_species(prec, tol, lanes):
     n, D, dt = 50000, 4e-5, 0.1
     x = W.positions(n, 3, 55)
     M = W.masses(n, 8, 55)
     if prec == F32:
         x, M = f32(x), f32(M)
-    ens = make(dim=3, S=8, rw=1.0, prec=prec, seed=55)
+    ens = make(dim=3, S=8, rw=1.0, prec=prec, seed=55, lanes=lanes)
     ens.init([n], x, M)
     ens.step(dt, D, 1)
     pos = ens.positions()
