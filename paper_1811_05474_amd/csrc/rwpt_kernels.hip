@@ -50,8 +50,22 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
   }
 }
 
-__device__ __forceinline__ void sincospi_t(float x, float* s, float* c) { sincospif(x, s, c); }
-__device__ __forceinline__ void sincospi_t(double x, double* s, double* c) { sincospi(x, s, c); }
+// Box-Muller pair from the uniforms (u, v): sqrt(-2 ln u) (cos 2 pi v, sin 2 pi v).
+// Binary32 uses the hardware log2 / sqrt / sin / cos (sin and cos take the
+// angle in revolutions), accurate to ~1e-6 relative -- far below what a
+// random displacement needs; binary64 uses the library functions.
+__device__ __forceinline__ void box_muller(float u, float v, float* z0, float* z1) {
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u));  // -2 ln 2 log2 u
+  *z0 = r * __builtin_amdgcn_cosf(v);
+  *z1 = r * __builtin_amdgcn_sinf(v);
+}
+__device__ __forceinline__ void box_muller(double u, double v, double* z0, double* z1) {
+  const double r = sqrt(-2.0 * log(u));
+  double sn, cs;
+  sincospi(2.0 * v, &sn, &cs);
+  *z0 = r * cs;
+  *z1 = r * sn;
+}
 
 // Three standard normals for (particle id, step) under the 64-bit seed:
 // counter (id, step lo, step hi, 0); uniforms u = w * 2^-32 + 2^-33;
@@ -64,19 +78,13 @@ __device__ __forceinline__ void walk_normals(uint32_t pid, uint64_t seed, uint64
   const T half = (T)1.16415321826934814453125e-10; // 2^-33
   const T u0 = (T)c[0] * s32 + half;
   const T u1 = (T)c[1] * s32 + half;
-  const T ra = sqrt((T)-2 * log(u0));
-  T sn, cs;
-  sincospi_t((T)2 * u1, &sn, &cs);
-  z[0] = ra * cs;
-  z[1] = ra * sn;
+  box_muller(u0, u1, &z[0], &z[1]);
   z[2] = (T)0;
   if constexpr (DIM > 2) {
     const T u2 = (T)c[2] * s32 + half;
     const T u3 = (T)c[3] * s32 + half;
-    const T rb = sqrt((T)-2 * log(u2));
-    T sn2, cs2;
-    sincospi_t((T)2 * u3, &sn2, &cs2);
-    z[2] = rb * cs2;
+    T unused;
+    box_muller(u2, u3, &z[2], &unused);
   }
 }
 
@@ -200,7 +208,21 @@ __global__ __launch_bounds__(kBlock) void k_walk_key(
   }
   const uint32_t key = (uint32_t)(P.cell_off + c);
   key_out[p] = key;
-  slot_out[p] = atomicAdd(&cell_count[key], 1u);
+  // The input is in cell order from the previous step, so equal new keys
+  // mostly sit in runs of consecutive lanes: one atomic per run, the run's
+  // lanes take consecutive slots.  (Active lanes are a prefix of the wave.)
+  const int lane = threadIdx.x & 63;
+  const uint32_t prev = __shfl_up(key, 1);
+  const unsigned long long starts = __ballot(lane == 0 || prev != key);
+  const unsigned long long active = __ballot(1);
+  const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);  // lanes 0..lane
+  const int rs = 63 - __clzll(starts & upto);
+  const unsigned long long above = starts & ~upto;
+  const int re = above ? __ffsll(above) - 1 : 64 - __clzll(active);
+  uint32_t base = 0;
+  if (lane == rs) base = atomicAdd(&cell_count[key], (uint32_t)(re - rs));
+  base = __shfl(base, rs);
+  slot_out[p] = base + (uint32_t)(lane - rs);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,14 +247,17 @@ __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t* s
   return v + base;
 }
 
+// Coalesced block sums: thread t adds elements t, t + 256, ... of the chunk.
 __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ cnt, int64_t n,
                                                         uint32_t* __restrict__ partials) {
   __shared__ uint32_t sh[4];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x;
   uint32_t s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i)
-    if (base + i < n) s += cnt[base + i];
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t k = base + (int64_t)i * kBlock;
+    if (k < n) s += cnt[k];
+  }
   uint32_t total;
   block_inclusive_scan(s, sh, &total);
   if (threadIdx.x == 0) partials[blockIdx.x] = total;
@@ -260,28 +285,51 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(uint32_t* __restrict__ part
   if (threadIdx.x == 0) start[n] = total;
 }
 
+// LDS index of chunk element k with one pad word per 16, so that thread t
+// reading its 16 consecutive elements hits distinct banks.
+__device__ __forceinline__ int scan_pad(int k) { return k + (k >> 4); }
+
+// Final pass: coalesced striped loads into LDS, a sequential scan of 16
+// consecutive elements per thread, a block scan of the thread sums, then
+// coalesced striped stores of the cell starts; the counts are re-zeroed for
+// the next step.
 __global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t* __restrict__ cnt, int64_t n,
                                                        const uint32_t* __restrict__ partials,
                                                        uint32_t* __restrict__ start) {
   __shared__ uint32_t sh[4];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t s = 0;
+  __shared__ uint32_t buf[kScanChunk + kScanChunk / 16];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    v[i] = (base + i < n) ? cnt[base + i] : 0u;
-    s += v[i];
+    const int k = t + i * kBlock;
+    buf[scan_pad(k)] = (base + k < n) ? cnt[base + k] : 0u;
+  }
+  __syncthreads();
+  uint32_t v[kScanItems];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = buf[scan_pad(t * kScanItems + i)];
+    sum += v[i];
   }
   uint32_t total;
-  const uint32_t incl = block_inclusive_scan(s, sh, &total);
-  uint32_t run = partials[blockIdx.x] + incl - s;
+  const uint32_t incl = block_inclusive_scan(sum, sh, &total);
+  uint32_t run = partials[blockIdx.x] + incl - sum;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i)
-    if (base + i < n) {
-      start[base + i] = run;
-      run += v[i];
-      cnt[base + i] = 0u;  // ready for the next step's counting
+  for (int i = 0; i < kScanItems; ++i) {
+    buf[scan_pad(t * kScanItems + i)] = run;
+    run += v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int k = t + i * kBlock;
+    if (base + k < n) {
+      start[base + k] = buf[scan_pad(k)];
+      cnt[base + k] = 0u;  // ready for the next step's counting
     }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1178,14 +1226,18 @@ __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ par
   __syncthreads();
   if (!last) return;
   __threadfence();
-  for (int r = 0; r < n_real; ++r) {
+  // one wave per realisation: lanes stride over its chunk partials, then a
+  // fixed butterfly
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = wave; r < n_real; r += kBlock / 64) {
     const int c0 = chunk_start[r], c1 = chunk_start[r + 1];
     for (int v = 0; v < S1; ++v) {
       double s = 0.0;
-      for (int c = c0 + threadIdx.x; c < c1; c += kBlock)
+      for (int c = c0 + lane; c < c1; c += 64)
         s += __hip_atomic_load(&chunk_part[(int64_t)c * S1 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s = block_sum(s, sh);
-      if (threadIdx.x == 0) out[(int64_t)r * S1 + v] = s;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) s += __shfl_xor(s, off);
+      if (lane == 0) out[(int64_t)r * S1 + v] = s;
     }
   }
   if (threadIdx.x == 0) {
