@@ -10,6 +10,14 @@ Prints one JSON line.  value = particle-pair interactions per second (unordered
 pairs {i, j}, i != j, within the cutoff, counted by the library before and
 after the timed region) on the FP32 path; steps/s and the FP64 path's numbers
 are reported beside it.
+
+--workload NAME measures another of the named workloads in the same form: the
+interface verification problem (75 realisations of 2000 particles in 1-D),
+the 64-realisation batch, the 3-D eight-species case, the 1-D sparse case or
+the 1-D full matrix on matrix cores.  For the full matrix the pair count is
+every pair of the realisation, and the roofline counts the pairs whose weight
+is at least 2^-40 (separation within sqrt(40 ln 2) sigma), the ones the kernel
+must evaluate to binary32 accuracy.
 """
 from __future__ import annotations
 
@@ -59,17 +67,31 @@ def parse():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--tile-lanes", type=int, default=0)
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="workload name (default %s)" % WORKLOAD)
     return ap.parse_args()
+
+
+def ensemble_for(rwpt, w, precision, tile_lanes, kappa=None):
+    kappa = w.kappa if kappa is None else kappa
+    return rwpt.Ensemble(dim=w.dim, n_species=w.n_species, react=w.react, kappa=kappa,
+                         rw_ratio=w.rw_ratio, precision=precision, seed=w.seed, tile_lanes=tile_lanes,
+                         box_lo=w.box_lo, box_hi=w.box_hi)
+
+
+def init_ensemble(ens, W, w):
+    x, M, sizes, Ds = W.make_inputs(w)
+    d_scale = Ds / w.D if w.D > 0 else None
+    ens.init(sizes, x, M, d_scale=d_scale)
+    return sizes
 
 
 def run_path(rwpt, W, w, precision, steps, warmup, tile_lanes, profile=True):
     import torch
 
-    x, M, sizes, _ = W.make_inputs(w)
-    ens = rwpt.Ensemble(dim=w.dim, n_species=w.n_species, react=w.react, kappa=w.kappa,
-                        rw_ratio=w.rw_ratio, precision=precision, seed=w.seed, tile_lanes=tile_lanes)
-    ens.init(sizes, x, M)
-    audit0 = ens.audit()[0].tolist()
+    ens = ensemble_for(rwpt, w, precision, tile_lanes)
+    init_ensemble(ens, W, w)
+    audit0 = ens.audit().sum(axis=0).tolist()
     ens.step(w.dt, w.D, warmup)
     ens.sync()
     pairs0, evals0 = ens.count_pairs(w.dt, w.D)
@@ -100,36 +122,54 @@ def run_path(rwpt, W, w, precision, steps, warmup, tile_lanes, profile=True):
         rwpt.rwpt_profile_enable(ens.ctx, False)
         out["phases"] = {k: {"ms_total": v[0], "launches": v[1],
                              "us_avg": (1e3 * v[0] / v[1]) if v[1] else 0.0} for k, v in prof.items() if v[1]}
-    out["audit"] = ens.audit()[0].tolist()
+    out["audit"] = ens.audit().sum(axis=0).tolist()
     out["tiling"] = rwpt.rwpt_get_tiling(ens.ctx)
     ens.close()
     return out
 
 
-def cpu_baseline(W, w, unordered_pairs_per_step):
+def cpu_baseline(W, w, unordered_pairs_per_step, budget_s=15.0):
     """The oracle (unchanged) on the host: one full step (walk + transfer +
     reaction) of the same workload, timed; pairs/s uses the workload's
-    in-cutoff pair count per step."""
+    in-cutoff pair count per step.  Realisations of a batch are stepped in
+    order until the time budget is spent, the pair count scaled by the
+    fraction of particles stepped."""
     import oracle
 
-    x, M, sizes, _ = W.make_inputs(w)
+    x, M, sizes, Ds = W.make_inputs(w)
     x = x.astype(np.float32).astype(np.float64)
-    ids = np.arange(w.n, dtype=np.uint32)
+    N = x.shape[0]
+    off = np.concatenate([[0], np.cumsum(sizes)])
     threads = oracle.num_threads()
-    steps = 1
+    done, passes = 0, 0
     t0 = time.perf_counter()
-    for s in range(steps):
-        x = oracle.walk(x, ids, w.seed, s, w.rw_ratio * w.D, w.dt, w.box_lo, w.box_hi)
-        M = oracle.transfer(x, M, w.D, w.dt, kappa=w.kappa, prec=32, react=w.react)
-    dt_s = (time.perf_counter() - t0) / steps
+    while True:  # repeat short workloads to at least a second of work
+        for r in range(len(sizes)):
+            b, e = int(off[r]), int(off[r + 1])
+            if e == b:
+                continue
+            xr = x[b:e]
+            if w.rw_ratio > 0:
+                ids = np.arange(b, e, dtype=np.uint32)
+                xr = oracle.walk(xr, ids, w.seed, 0, w.rw_ratio * Ds[r], w.dt, w.box_lo, w.box_hi)
+            oracle.transfer(xr, M[:, b:e], Ds[r], w.dt, kappa=w.kappa, prec=32, react=w.react)
+            done += e - b
+            if time.perf_counter() - t0 > budget_s:
+                break
+        passes += 1
+        if done < passes * N or time.perf_counter() - t0 > 1.0:
+            break
+    dt_s = time.perf_counter() - t0
+    frac = done / N  # steps' worth of particles processed
+    sample = ("%d full step(s) (walk + transfer + reaction, FP64 weights) of %d of %d particles"
+              % (passes, min(done, N), N))
     return {
-        "value": unordered_pairs_per_step / dt_s,
+        "value": frac * unordered_pairs_per_step / dt_s,
         "unit": "pair-interactions/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": "%d full step (walk + transfer + reaction, FP64 weights) of the 1e6-particle 2-D "
-                  "workload on %d OpenMP threads: %.3f s/step" % (steps, threads, dt_s),
-        "steps_per_s": 1.0 / dt_s,
+        "sample": "%s of workload %s on %d OpenMP threads: %.3f s" % (sample, w.name, threads, dt_s),
+        "steps_per_s": frac / dt_s,
     }
 
 
@@ -169,7 +209,11 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.init()
-    w = W.WORKLOADS[WORKLOAD]
+    if args.workload not in W.WORKLOADS:
+        print("bench.py: unknown workload %r (known: %s)" % (args.workload, ", ".join(W.WORKLOADS)),
+              file=sys.stderr)
+        sys.exit(2)
+    w = W.WORKLOADS[args.workload]
 
     if args.copy_calibration_mib:
         nbytes = args.copy_calibration_mib << 20
@@ -194,26 +238,44 @@ def main():
     steps_per_s = 1e3 / r32["ms_per_step"]
     value = unordered * steps_per_s
 
-    ex = r32["phases"]["exchange"]
-    flops_per_launch = exchange_flops_per_pair(w.dim, w.n_species) * r32["ordered_pairs_per_step"]
+    dense = "dense" in r32["phases"]
+    if dense:
+        # pairs the full-matrix kernel must evaluate: weight >= 2^-40
+        counter = ensemble_for(rwpt, w, rwpt.RWPT_FP32, 0, kappa=math.sqrt(40.0 * math.log(2.0)))
+        init_ensemble(counter, W, w)
+        if w.rw_ratio > 0:  # same walk, same positions as the measured run
+            counter.step(w.dt, w.D, args.warmup + 2 * args.steps)
+        alg_pairs, _ = counter.count_pairs(w.dt, w.D)
+        counter.close()
+        ex = r32["phases"]["dense"]
+        kernel = "dense path (tile bounds + row sums + bf16-split MFMA exchange + reaction)"
+    else:
+        alg_pairs = r32["ordered_pairs_per_step"]
+        ex = r32["phases"]["exchange"]
+        kernel = "k_exchange (weights + exchange + reaction + audit partials)"
+    n_total = r32["masses"].shape[1]
+    flops_per_launch = exchange_flops_per_pair(w.dim, w.n_species) * alg_pairs
     achieved_tflops = flops_per_launch / (ex["us_avg"] * 1e-6) / 1e12
+    alg_bytes = exchange_bytes_per_particle(w.dim, w.n_species, 4) * n_total
     roofline = {
         "bound": "alu",
-        "kernel": "k_exchange (weights + exchange + reaction + audit partials)",
+        "kernel": kernel,
         "achieved": achieved_tflops,
         "peak": PEAK_FP32_VECTOR_TFLOPS,
         "unit": "TFLOP/s",
         "frac": achieved_tflops / PEAK_FP32_VECTOR_TFLOPS,
-        "traffic": measured_traffic("k_exchange_walk2d_n1e6"),
+        "traffic": measured_traffic("k_exchange_" + w.name),
         "us_per_launch": ex["us_avg"],
         "flops_per_launch": flops_per_launch,
-        "algorithmic_bytes_per_launch": exchange_bytes_per_particle(w.dim, w.n_species, 4) * w.n,
-        "hbm_frac_of_algorithmic_bytes": exchange_bytes_per_particle(w.dim, w.n_species, 4) * w.n
-        / (ex["us_avg"] * 1e-6) / 1e9 / PEAK_HBM_GBPS,
+        "algorithmic_bytes_per_launch": alg_bytes,
+        "hbm_frac_of_algorithmic_bytes": alg_bytes / (ex["us_avg"] * 1e-6) / 1e9 / PEAK_HBM_GBPS,
     }
+    if dense:
+        roofline["ordered_pairs_evaluated_per_launch"] = alg_pairs
 
     line = {
-        "metric": METRIC,
+        "metric": METRIC if w.name == WORKLOAD else
+        "particle-pair interactions/s and steps/s, workload %s; FP32 vs FP64 path" % w.name,
         "value": value,
         "unit": "pair-interactions/s",
         "n_gpus": 1,
@@ -227,9 +289,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": WORKLOAD, "n_particles": w.n, "dim": w.dim, "species": w.n_species,
-            "D": w.D, "dt": w.dt, "kappa": w.kappa, "rw_ratio": w.rw_ratio, "norm": "sym",
-            "reaction": "A+B->0", "tile_lanes": r32["tiling"][0], "cell_refine": r32["tiling"][1],
+            "workload": w.name, "n_particles": n_total, "realisations": w.n_real, "dim": w.dim,
+            "species": w.n_species, "D": w.D, "dt": w.dt,
+            "kappa": w.kappa if math.isfinite(w.kappa) else "inf", "rw_ratio": w.rw_ratio,
+            "norm": "sym", "reaction": "A+B->0" if w.react else "none",
+            "path": "dense" if dense else "sparse",
+            "tile_lanes": r32["tiling"][0], "cell_refine": r32["tiling"][1],
             "unordered_pairs_per_step": unordered,
             "candidate_evaluations_per_step": r32["evaluations_per_step"],
         },
@@ -248,7 +313,11 @@ def main():
         }
         for tag, r in (("fp32", r32), ("fp64", r64)):
             a0, a1 = r["audit0"], r["audit"]
-            line["fp64"]["a_minus_b_drift_" + tag] = abs(a1[2] - a0[2]) / (a0[0] + a0[1])
+            if w.react:
+                line["fp64"]["a_minus_b_drift_" + tag] = abs(a1[-1] - a0[-1]) / (a0[0] + a0[1])
+            else:
+                line["fp64"]["species_drift_" + tag] = max(abs(a1[k] - a0[k]) / abs(a0[k])
+                                                           for k in range(w.n_species) if a0[k])
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, w, unordered)
     print(json.dumps(line))

@@ -36,6 +36,7 @@ class Workload:
     box_hi: tuple = (1.0, 1.0, 1.0)
     n_real: int = 1
     D_choices: tuple = field(default_factory=tuple)
+    init: str = "uniform"  # "uniform" masses, or the segregated "interface" of Sec. 3
 
 
 WORKLOADS = {
@@ -43,6 +44,8 @@ WORKLOADS = {
     "plain1d_n2000": Workload("plain1d_n2000", 1, 2000, 2, 1e-4, 0.1, 100, math.inf, 0.0, 1000),
     # 1-D, N = 32768: dense full-matrix and sparse kappa = 3 paths
     "plain1d_n32768": Workload("plain1d_n32768", 1, 32768, 2, 1e-4, 0.1, 500, 3.0, 0.0, 2000),
+    # the same particles with every pair interacting (full matrix, no cutoff)
+    "full1d_n32768": Workload("full1d_n32768", 1, 32768, 2, 1e-4, 0.1, 500, math.inf, 0.0, 2000),
     # 2-D, N = 10^6 in the unit square, kappa = 3, random walk between transfers
     "walk2d_n1e6": Workload("walk2d_n1e6", 2, 1_000_000, 2, 1e-5, 0.1, 200, 3.0, 1.0, 3000),
     # 64 independent 2-D realisations, N log-uniform in [1e4, 2e5], D in {1e-5, 1e-4}
@@ -50,7 +53,25 @@ WORKLOADS = {
                            D_choices=(1e-5, 1e-4)),
     # 3-D, N = 8e6, eight species, reaction on the first pair
     "walk3d_n8e6_s8": Workload("walk3d_n8e6_s8", 3, 8_000_000, 8, 1e-6, 0.1, 50, 3.0, 1.0, 5000),
+    # the paper's verification problem (Sec. 3): segregated interface on
+    # [0, 50], total D = 1 split equally between transfer and walk, t = 10;
+    # species are the conservative components C1, C2 (no reaction term)
+    "interface1d_l50": Workload("interface1d_l50", 1, 2000, 2, 0.5, 0.1, 100, 3.0, 1.0, 6000,
+                                react=None, box_hi=(50.0, 1.0, 1.0), n_real=75, init="interface"),
 }
+
+
+def interface(n: int, dim: int, L, seed: int):
+    """Segregated initial condition of the paper's test problem (Sec. 3, 5.1):
+    uniform positions in [0, L]^dim; C1 = 1 for x > L/2 (0 below), C2 the
+    complement; masses are concentration times the particle volume
+    ds = |box| / n.  Returns positions (n, dim) and masses (2, n)."""
+    L = np.broadcast_to(np.asarray(L, dtype=np.float64), (dim,))
+    x = positions(n, dim, seed, (0.0,) * dim, tuple(L))
+    ds = float(np.prod(L)) / n
+    right = x[:, 0] > 0.5 * L[0]
+    M = np.stack([right * ds, (~right) * ds]).astype(np.float64)
+    return x, M
 
 
 def positions(n: int, dim: int, seed: int, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> np.ndarray:
@@ -80,7 +101,13 @@ def make_inputs(w: Workload, n: int | None = None):
     """Positions (N, dim), masses (S, N), per-realisation sizes and D values.
 
     ``n`` overrides the particle count of a single-realisation workload (for
-    scaled-down parity cases)."""
+    scaled-down parity cases).  Realisation r of an "interface" workload is
+    drawn with seed w.seed + r."""
+    if w.init == "interface":
+        n = w.n if n is None else int(n)
+        parts = [interface(n, w.dim, w.box_hi[:w.dim], w.seed + r) for r in range(w.n_real)]
+        return (np.concatenate([p[0] for p in parts], 0), np.concatenate([p[1] for p in parts], 1),
+                np.full(w.n_real, n, dtype=np.int64), np.full(w.n_real, w.D))
     if w.n_real == 1:
         n = w.n if n is None else int(n)
         x = positions(n, w.dim, w.seed, w.box_lo, w.box_hi)

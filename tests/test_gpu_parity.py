@@ -468,3 +468,71 @@ def test_dense_path_requires_full_matrix_binary32_single_realisation():
         ens.init([10, 10], W.positions(20, 1, 1), W.masses(20, 2, 1))
     assert ei.value.status == rwpt.RWPT_EUNSUPPORTED
     ens.close()
+
+
+# ------------------------------------------ interface verification (Sec. 3) ----
+
+def interface_ensemble(n, n_real, seed0):
+    parts = [W.interface(n, 1, 50.0, seed0 + r) for r in range(n_real)]
+    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts], 1)
+
+
+@pytest.mark.parametrize("prec,tol", [(F32, 1e-5), (F64, 1e-12)])
+def test_interface_steps_replayed(prec, tol):
+    # three realisations with the walk: each step's walk against the oracle's
+    # walk (global particle ids), the transfer on the positions the GPU stored
+    n, R, seed = 2000, 3, 6000
+    x, M = interface_ensemble(n, R, seed)
+    if prec == F32:
+        x, M = f32(x), f32(M)
+    ens = make(dim=1, react=None, rw=1.0, prec=prec, seed=seed, box_hi=(50.0, 1, 1))
+    ens.init([n] * R, x, M)
+    xcur, mcur = x, M
+    for step in range(4):
+        ens.step(0.1, 0.5, 1)
+        pos, got = ens.positions(), ens.masses()
+        walked = oracle.walk(xcur, np.arange(n * R), seed, step, 0.5, 0.1, (0.0,), (50.0,))
+        # binary32 positions up to 50 carry 2e-6 relative rounding per move
+        assert np.abs(pos - walked).max() < (1e-4 if prec == F32 else 1e-12)
+        for r in range(R):
+            b, e = r * n, (r + 1) * n
+            ref = oracle.transfer(pos[b:e], mcur[:, b:e], 0.5, 0.1, kappa=3.0,
+                                  prec=32 if prec == F32 else 64, react=None)
+            assert normerr(got[:, b:e], ref) < tol, (step, r)
+        xcur, mcur = pos, got
+    ens.close()
+
+
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_interface1d_l50_matches_erfc(prec):
+    # the full verification workload: 75 realisations of N = 2000 on [0, 50],
+    # D = 1 split equally between transfer and walk, 100 steps to t = 10.
+    # The oracle's ensemble gives a per-realisation RMSE of 0.012 and a binned
+    # ensemble profile within 0.0017 (RMS) of erfc.
+    from scipy.special import erfc
+    w = W.WORKLOADS["interface1d_l50"]
+    L, n, R = w.box_hi[0], w.n, w.n_real
+    x, M, sizes, _ = W.make_inputs(w)
+    assert np.array_equal(x, interface_ensemble(n, R, w.seed)[0])
+    ds = L / n
+    ens = make(dim=1, react=None, rw=w.rw_ratio, prec=prec, seed=w.seed, box_hi=w.box_hi)
+    ens.init(sizes, x, M)
+    a0 = ens.audit()
+    ens.step(w.dt, w.D, w.steps)
+    pos, got = ens.positions()[:, 0], ens.masses()
+    a1 = ens.audit()
+    # the two components stay complementary and each is conserved per realisation
+    assert np.abs((got[0] + got[1]) / ds - 1.0).max() < (1e-5 if prec == F32 else 1e-12)
+    assert np.abs(a1[:, :2] - a0[:, :2]).max() < (1e-5 if prec == F32 else 1e-12) * L
+    c = got[0] / ds
+    exact = 0.5 * erfc((0.5 * L - pos) / math.sqrt(4 * (2 * w.D) * w.steps * w.dt))
+    per_real = np.sqrt(np.mean(((c - exact) ** 2).reshape(R, n), axis=1))
+    assert per_real.mean() < 0.02 and per_real.max() < 0.04
+    bins = np.linspace(0.0, L, 51)
+    b = np.clip(np.digitize(pos, bins) - 1, 0, 49)
+    prof = np.bincount(b, c, 50) / np.bincount(b, None, 50)
+    mid = 0.5 * (bins[1:] + bins[:-1])
+    ex_mid = 0.5 * erfc((0.5 * L - mid) / math.sqrt(4 * (2 * w.D) * w.steps * w.dt))
+    assert math.sqrt(np.mean((prof - ex_mid) ** 2)) < 0.004
+    assert np.abs(prof - ex_mid).max() < 0.012
+    ens.close()
