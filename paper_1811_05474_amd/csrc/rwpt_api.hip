@@ -18,6 +18,7 @@
 
 #include "rwpt.h"
 #include "rwpt_kernels.h"
+#include "rwpt_layout.h"
 
 using namespace rwpt;
 
@@ -74,6 +75,7 @@ struct rwpt_ctx {
   std::vector<double> d_scale;
 
   DevBuf pos0, pos1, mass0, mass1, id, key, slot, tmp_src, tmp_id, tmp_key, skey, r, q;
+  DevBuf nb_meta, nb_idx, nb_w;  // neighbour cache of the one-lane-per-particle kernels
   DevBuf cell_count, cell_start, scan_part;
   DevBuf d_rp, d_st, d_tiles, d_tile_start, d_real_start;
   DevBuf audit_part, audit_out, step_ctr, counts, d_chunks, d_chunk_start, chunk_part, audit_done;
@@ -149,13 +151,16 @@ static int lanes_to_log2(int lanes) {
 
 static void default_refine(int dim, double out[3]) {
   // cells per cutoff length: fine along x (the fastest key axis, which trims
-  // the candidate ranges), a few per cutoff across the other axes
+  // the candidate ranges), a few per cutoff across the other axes in 1-D and
+  // 2-D
   if (dim == 1) {
     out[0] = 16.0; out[1] = 1.0; out[2] = 1.0;
   } else if (dim == 2) {
     out[0] = 16.0; out[1] = 2.0; out[2] = 1.0;
   } else {
-    out[0] = 2.0; out[1] = 1.0; out[2] = 1.0;
+    // 3-D neighbourhoods are sparse (one lane per particle): cells of two
+    // cutoffs, so each particle's cutoff box overlaps 2 x 2 rows of 2 cells
+    out[0] = 0.5; out[1] = 0.5; out[2] = 0.5;
   }
 }
 
@@ -298,6 +303,7 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
       P.escale_f = (float)(-1.4426950408889634073599246810019 / sigma2);
       // geometric cutoff: covers the rounding of s^2 in the predicate
       rcg = std::sqrt(rc2) * (1.0 + 1e-5);
+      P.rc_geo = rcg;
       if (c->dense) {
         // every pair counts; the grid only orders particles so that 32-particle
         // column tiles are compact, and tiles farther apart than the distance
@@ -383,6 +389,11 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   HIPCHK(c, c->d_tile_start.ensure(c->h_tile_start.size() * sizeof(int32_t)));
   HIPCHK(c, c->audit_part.ensure((size_t)std::max(1, c->ntiles) * (c->S + 1) * sizeof(double)));
   HIPCHK(c, c->counts.ensure((size_t)std::max(1, c->ntiles) * 2 * sizeof(unsigned long long)));
+  if (c->log2l == kPrivateLists) {
+    HIPCHK(c, c->nb_meta.ensure((size_t)c->cap * sizeof(uint16_t)));
+    HIPCHK(c, c->nb_idx.ensure((size_t)std::max(1, c->ntiles) * kCacheWave * sizeof(uint32_t)));
+    HIPCHK(c, c->nb_w.ensure((size_t)std::max(1, c->ntiles) * kCacheWave * c->tsize));
+  }
   if (c->dense) {
     const int ncb = dense_ncb(c->S, c->cfg.norm);
     HIPCHK(c, c->bbox.ensure((size_t)(c->cap / kDenseColTile + 1) * 2 * c->dim * sizeof(float)));
@@ -441,6 +452,9 @@ static PairArgs pair_args(rwpt_ctx* c) {
   a.norm = c->cfg.norm;
   a.audit_part = c->audit_part.as<double>();
   a.counts = c->counts.as<unsigned long long>();
+  a.nb_meta = c->nb_meta.as<uint16_t>();
+  a.nb_idx = c->nb_idx.as<uint32_t>();
+  a.nb_w = c->nb_w.p;
   return a;
 }
 
@@ -485,7 +499,7 @@ static rwpt_status enqueue_step(rwpt_ctx* c, bool sort, bool walk) {
     rwpt_status st = enqueue_sort(c, walk);
     if (st != RWPT_OK) return st;
   } else {
-    HIPCHK(c, hipMemcpyAsync(c->mass1.p, c->mass0.p, (size_t)c->S * c->cap * c->tsize,
+    HIPCHK(c, hipMemcpyAsync(c->mass1.p, c->mass0.p, (size_t)padded_species(c->S) * c->cap * c->tsize,
                              hipMemcpyDeviceToDevice, c->stream));
   }
   PairArgs a = pair_args(c);
@@ -512,7 +526,9 @@ static rwpt_status enqueue_step(rwpt_ctx* c, bool sort, bool walk) {
     PhaseScope ps(c, PH_DENSE);
     HIPCHK(c, launch_dense_step(c->dim, da, c->stream));
   } else {
-    if (c->cfg.norm == RWPT_NORM_SYM) {
+    // the one-lane-per-particle exchange reads the row-sum pass's neighbour
+    // cache, so that pass runs for either normalisation
+    if (c->cfg.norm == RWPT_NORM_SYM || c->log2l == kPrivateLists) {
       PhaseScope ps(c, PH_ROWSUM);
       HIPCHK(c, launch_rowsum(fp64, c->dim, c->log2l, a, c->stream));
     }
@@ -534,7 +550,7 @@ static rwpt_status ensure_sorted(rwpt_ctx* c) {
   rwpt_status st = enqueue_sort(c, false);
   if (st != RWPT_OK) return st;
   // enqueue_sort leaves masses in mass1; bring them back to mass0
-  HIPCHK(c, hipMemcpyAsync(c->mass0.p, c->mass1.p, (size_t)c->S * c->cap * c->tsize,
+  HIPCHK(c, hipMemcpyAsync(c->mass0.p, c->mass1.p, (size_t)padded_species(c->S) * c->cap * c->tsize,
                            hipMemcpyDeviceToDevice, c->stream));
   c->sorted_valid = true;
   return RWPT_OK;
@@ -679,12 +695,13 @@ rwpt_status rwpt_init_ensemble(rwpt_ctx* c, int32_t n_real, const int64_t* n_per
   c->dense = dense_ok && c->cfg.path != RWPT_PATH_SPARSE;
   c->cap = std::max<int64_t>(64, (N + 63) / 64 * 64);
   const size_t ts = c->tsize, cap = (size_t)c->cap;
-  HIPCHK(c, c->pos0.ensure(dim * cap * ts));
-  HIPCHK(c, c->pos1.ensure(dim * cap * ts));
-  const int Sa = padded_species(S);
+  const int PS = dim == 3 ? 4 : dim;  // position slots per particle (particle-major)
+  HIPCHK(c, c->pos0.ensure(PS * cap * ts));
+  HIPCHK(c, c->pos1.ensure(PS * cap * ts));
+  const int Sa = padded_species(S);  // species slots per particle
   HIPCHK(c, c->mass0.ensure(Sa * cap * ts));
   HIPCHK(c, c->mass1.ensure(Sa * cap * ts));
-  // padding species rows stay zero for the lifetime of the ensemble
+  // unused species slots stay zero for the lifetime of the ensemble
   HIPCHK(c, hipMemsetAsync(c->mass0.p, 0, Sa * cap * ts, c->stream));
   HIPCHK(c, hipMemsetAsync(c->mass1.p, 0, Sa * cap * ts, c->stream));
   HIPCHK(c, c->id.ensure(cap * 4));
@@ -699,8 +716,8 @@ rwpt_status rwpt_init_ensemble(rwpt_ctx* c, int32_t n_real, const int64_t* n_per
   HIPCHK(c, c->d_real_start.ensure((n_real + 1) * sizeof(int64_t)));
   HIPCHK(c, c->audit_out.ensure((size_t)n_real * (S + 1) * sizeof(double)));
 
-  // host staging: SoA in the path's precision
-  std::vector<unsigned char> hp(dim * cap * ts, 0), hm(S * cap * ts, 0);
+  // host staging: particle-major in the path's precision
+  std::vector<unsigned char> hp(PS * cap * ts, 0), hm(Sa * cap * ts, 0);
   std::vector<uint32_t> hid(cap, 0);
   c->audit_init.assign((size_t)n_real * (S + 1), 0.0);
   std::vector<double> rounded_mass((size_t)N * S);
@@ -708,18 +725,18 @@ rwpt_status rwpt_init_ensemble(rwpt_ctx* c, int32_t n_real, const int64_t* n_per
     hid[i] = (uint32_t)i;
     for (int k = 0; k < dim; ++k) {
       const double v = pos[i * dim + k];
-      if (ts == 8) ((double*)hp.data())[k * cap + i] = v;
-      else ((float*)hp.data())[k * cap + i] = (float)v;
+      if (ts == 8) ((double*)hp.data())[PS * i + k] = v;
+      else ((float*)hp.data())[PS * i + k] = (float)v;
     }
     for (int s = 0; s < S; ++s) {
       const double v = mass[(size_t)s * N + i];
       double vr;
       if (ts == 8) {
-        ((double*)hm.data())[s * cap + i] = v;
+        ((double*)hm.data())[Sa * i + s] = v;
         vr = v;
       } else {
         const float f = (float)v;
-        ((float*)hm.data())[s * cap + i] = f;
+        ((float*)hm.data())[Sa * i + s] = f;
         vr = (double)f;
       }
       rounded_mass[(size_t)s * N + i] = vr;
@@ -807,11 +824,14 @@ rwpt_status rwpt_sync(rwpt_ctx* c) {
   return RWPT_OK;
 }
 
-static rwpt_status fetch_sorted(rwpt_ctx* c, const DevBuf& buf, int comps, double* out, bool species_major) {
+// Copy `comps` components per particle (particle-major, `stride` slots per
+// particle on the device) back to the caller's order.
+static rwpt_status fetch_sorted(rwpt_ctx* c, const DevBuf& buf, int comps, int stride, double* out,
+                                bool species_major) {
   const int64_t N = c->N;
   if (N == 0) return RWPT_OK;
   const size_t ts = c->tsize, cap = (size_t)c->cap;
-  std::vector<unsigned char> h(comps * cap * ts);
+  std::vector<unsigned char> h(stride * cap * ts);
   std::vector<uint32_t> hid(N);
   HIPCHK(c, hipMemcpyAsync(h.data(), buf.p, h.size(), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(hid.data(), c->id.p, N * 4, hipMemcpyDeviceToHost, c->stream));
@@ -820,7 +840,8 @@ static rwpt_status fetch_sorted(rwpt_ctx* c, const DevBuf& buf, int comps, doubl
     const uint32_t o = hid[p];
     if ((int64_t)o >= N) return fail(c, RWPT_EDEVICE, "corrupt id map");
     for (int k = 0; k < comps; ++k) {
-      const double v = ts == 8 ? ((const double*)h.data())[k * cap + p] : (double)((const float*)h.data())[k * cap + p];
+      const size_t e = (size_t)stride * p + k;
+      const double v = ts == 8 ? ((const double*)h.data())[e] : (double)((const float*)h.data())[e];
       if (species_major) out[(size_t)k * N + o] = v;
       else out[(size_t)o * comps + k] = v;
     }
@@ -833,7 +854,7 @@ rwpt_status rwpt_query_masses(rwpt_ctx* c, double* out) {
   c->err.clear();
   if (!c->initialized) return fail(c, RWPT_ESTATE, "query before rwpt_init_ensemble");
   if (!out && c->N > 0) return fail(c, RWPT_EINVAL, "out is NULL");
-  return fetch_sorted(c, c->mass0, c->S, out, true);
+  return fetch_sorted(c, c->mass0, c->S, padded_species(c->S), out, true);
 }
 
 rwpt_status rwpt_query_positions(rwpt_ctx* c, double* out) {
@@ -841,7 +862,7 @@ rwpt_status rwpt_query_positions(rwpt_ctx* c, double* out) {
   c->err.clear();
   if (!c->initialized) return fail(c, RWPT_ESTATE, "query before rwpt_init_ensemble");
   if (!out && c->N > 0) return fail(c, RWPT_EINVAL, "out is NULL");
-  return fetch_sorted(c, c->pos0, c->dim, out, false);
+  return fetch_sorted(c, c->pos0, c->dim, c->dim == 3 ? 4 : c->dim, out, false);
 }
 
 rwpt_status rwpt_audit(rwpt_ctx* c, double* out) {
@@ -1023,7 +1044,7 @@ static std::vector<std::pair<int, std::array<double, 3>>> tuning_candidates(int 
   std::vector<std::array<double, 3>> refs;
   if (dim == 1) refs = {{4, 1, 1}, {8, 1, 1}, {16, 1, 1}, {32, 1, 1}};
   else if (dim == 2) refs = {{8, 1, 1}, {16, 1, 1}, {4, 2, 1}, {8, 2, 1}, {8, 3, 1}, {16, 3, 1}, {8, 4, 1}};
-  else refs = {{2, 1, 1}, {4, 1, 1}, {8, 1, 1}, {4, 2, 2}, {8, 0.5, 0.5}, {16, 0.5, 0.5}};
+  else refs = {{0.5, 0.5, 0.5}, {1, 0.5, 0.5}, {2, 1, 1}, {4, 1, 1}, {8, 1, 1}, {4, 2, 2}, {8, 0.5, 0.5}};
   std::vector<std::pair<int, std::array<double, 3>>> out;
   for (int lanes : {-1, 1, 4, 8, 16})
     for (auto& r : refs) out.push_back({lanes, r});
@@ -1097,7 +1118,7 @@ rwpt_status rwpt_autotune(rwpt_ctx* c, double dt, double D, int32_t trial_steps)
   // snapshot of the state the tuning steps will overwrite
   const size_t ts = c->tsize, cap = (size_t)c->cap;
   const int Sa = padded_species(c->S);
-  const size_t npos = c->dim * cap * ts, nmass = Sa * cap * ts, naud = (size_t)c->n_real * (c->S + 1) * 8;
+  const size_t npos = (c->dim == 3 ? 4 : c->dim) * cap * ts, nmass = Sa * cap * ts, naud = (size_t)c->n_real * (c->S + 1) * 8;
   DevBuf sp, sm, si, sa, sc;
   rwpt_status result = RWPT_OK;
   const rwpt_config saved_cfg = c->cfg;
@@ -1221,7 +1242,7 @@ void rwpt_destroy(rwpt_ctx* c) {
                       &c->cell_start, &c->scan_part, &c->d_rp, &c->d_st, &c->d_tiles,
                       &c->d_tile_start, &c->d_real_start, &c->audit_part, &c->audit_out,
                       &c->step_ctr, &c->counts, &c->d_chunks, &c->d_chunk_start, &c->chunk_part,
-                      &c->audit_done, &c->bbox, &c->bparts};
+                      &c->audit_done, &c->bbox, &c->bparts, &c->nb_meta, &c->nb_idx, &c->nb_w};
     for (DevBuf* b : bufs) b->release();
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }

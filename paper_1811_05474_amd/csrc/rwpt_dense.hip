@@ -22,6 +22,7 @@
 #include <type_traits>
 
 #include "rwpt_kernels.h"
+#include "rwpt_layout.h"
 
 namespace rwpt {
 
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_bbox(const float* __restrict__ 
   for (int k = 0; k < DIM; ++k) {
     float lo = INFINITY, hi = -INFINITY;
     for (int j = j0; j < j1; ++j) {
-      const float v = pos[k * cap + j];
+      const float v = pos[pos_stride<DIM>() * j + k];
       lo = fminf(lo, v);
       hi = fmaxf(hi, v);
     }
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rowsum(const float* __restrict
   const int ii = valid ? i : n - 1;
   float xi[DIM];
 #pragma unroll
-  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  for (int k = 0; k < DIM; ++k) xi[k] = pos[pos_stride<DIM>() * ii + k];
   // row box: union of the (up to) two column-tile boxes covering the rows
   float rbox[2 * DIM];
   load_box<DIM>(bbox, i0 / kColTile, rbox);
@@ -157,14 +158,14 @@ __global__ __launch_bounds__(kBlock) void k_dense_rowsum(const float* __restrict
       for (int u = 0; u < kColTile; ++u) {
         float xj[DIM];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) xj[k] = pos[k * cap + j0 + u];
+        for (int k = 0; k < DIM; ++k) xj[k] = pos[pos_stride<DIM>() * (j0 + u) + k];
         a += __builtin_amdgcn_exp2f(sep2f<DIM>(xi, xj) * escale);
       }
     } else {
       for (int j = j0; j < n; ++j) {
         float xj[DIM];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) xj[k] = pos[k * cap + j];
+        for (int k = 0; k < DIM; ++k) xj[k] = pos[pos_stride<DIM>() * j + k];
         a += __builtin_amdgcn_exp2f(sep2f<DIM>(xi, xj) * escale);
       }
     }
@@ -185,17 +186,18 @@ __global__ __launch_bounds__(kBlock) void k_dense_prep_b(const float* __restrict
   const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (j >= cap) return;
   const bool in = j < n;
+  const int64_t SP = species_slots(S);
   const float qj = in ? q[j] : 0.0f;
   for (int c = 0; c < NC; ++c) {
     float v = 0.0f;
     if (in) {
       if (norm == 0) {
-        if (c < S) v = mass[c * cap + j];
-        else if (c < 2 * S) v = qj * mass[(c - S) * cap + j];
+        if (c < S) v = mass[SP * j + c];
+        else if (c < 2 * S) v = qj * mass[SP * j + (c - S)];
         else if (c == 2 * S) v = qj;
         else if (c == 2 * S + 1) v = 1.0f;
       } else {
-        if (c < S) v = mass[c * cap + j];
+        if (c < S) v = mass[SP * j + c];
         else if (c == S) v = 1.0f;
       }
     }
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_exchange(
   const int ii = valid_i ? i : n - 1;
   float xi[DIM];
 #pragma unroll
-  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  for (int k = 0; k < DIM; ++k) xi[k] = pos[pos_stride<DIM>() * ii + k];
   float rbox[2 * DIM];
   load_box<DIM>(bbox, i0 / kColTile, rbox);
 
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_exchange(
       const int j = jb + e;
       float xj[DIM];
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) xj[k] = pos[k * cap + j];  // j < cap: rows past n are padding
+      for (int k = 0; k < DIM; ++k) xj[k] = pos[pos_stride<DIM>() * j + k];  // j < cap: rows past n are padding
       const float ww = __builtin_amdgcn_exp2f(sep2f<DIM>(xi, xj) * escale);
       w[e] = (valid_i && j < n) ? ww : 0.0f;
     }
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_exchange(
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       if (s >= S) continue;
-      const double Mi = (double)min_[s * cap + i];
+      const double Mi = (double)min_[species_slots(S) * (int64_t)i + s];
       double dm;
       if (norm == 0) dm = 0.25 * (qi * C[s] + C[S + s] - Mi * (qi * C[2 * S + 1] + C[2 * S]));
       else dm = 0.5 * (C[s] / C[S] - Mi);
@@ -312,7 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_exchange(
     for (int s = 0; s < 8; ++s) {
       if (s >= S) continue;
       const float v = (float)Mn[s];
-      mout[s * cap + i] = v;
+      mout[species_slots(S) * (int64_t)i + s] = v;
       tot[s] = (double)v;
       if (s == react_a) va = (double)v;
       if (s == react_b) vb = (double)v;

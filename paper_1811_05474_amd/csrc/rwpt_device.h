@@ -23,6 +23,7 @@ struct RealParams {
   float rc2_f;         // rc2_d rounded once to binary32
   float escale_f;      // -log2(e) / sigma^2 rounded to binary32 (for exp2)
   double amp;          // random-walk amplitude sqrt(2 D_rw dt)
+  double rc_geo;       // geometric cutoff sqrt(rc2_d) (1 + 1e-5): covers the rounding of s^2
 };
 
 // Offset (dy, dz) of a neighbour row of cells and how many cells (rx) to
@@ -39,10 +40,10 @@ struct Tile {
 // Arguments of the pair kernels.  Floating-point arrays are binary32 or
 // binary64 according to the kernel instantiation.
 struct PairArgs {
-  const void* pos;         // [dim][cap], cell-sorted
-  int64_t cap;             // leading dimension of the position / mass arrays
-  const void* mass_in;     // [S][cap]
-  void* mass_out;          // [S][cap]
+  const void* pos;         // [cap][PS] particle-major (PS = 1, 2, 4), cell-sorted
+  int64_t cap;             // particle capacity of the position / mass arrays
+  const void* mass_in;     // [cap][SP] particle-major (SP = 2, 4, 8 species slots)
+  void* mass_out;          // [cap][SP]
   const void* q_in;        // 1 / r_i for the symmetric normalisation, [cap]
   void* q_out;             // written by the row-sum pass
   double* r_out;           // r_i = sum_j w_ij, written by the row-sum pass
@@ -60,6 +61,11 @@ struct PairArgs {
   uint32_t* nbr_cursor;    // neighbour export: per-particle counts / write cursors
   const unsigned long long* nbr_rowptr;  // neighbour export: exclusive offsets
   uint32_t* nbr_pairs;     // neighbour export: (i, j) sorted-slot pairs
+  // neighbour cache of the one-lane-per-particle kernels (written by the
+  // row-sum pass, read by the exchange pass)
+  uint16_t* nb_meta;       // [cap]: (offset in the wave's region << 4) | count, or the miss code
+  uint32_t* nb_idx;        // [ntiles][kCacheWave] sorted index j of each cached neighbour
+  void* nb_w;              // [ntiles][kCacheWave] its weight w_ij (binary32 or binary64)
 };
 
 }  // namespace rwpt

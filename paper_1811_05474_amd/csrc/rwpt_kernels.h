@@ -48,15 +48,23 @@ hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
                         int64_t cap, const void* mass_in, void* mass_out, int32_t S,
                         uint32_t* id_out, uint32_t* skey, hipStream_t s);
 
-// Species rows the mass arrays hold for S species: the exchange kernel is
-// instantiated for 2, 4 or 8 species and reads every row of its instantiation,
-// so rows S..padded_species(S)-1 are allocated and kept at zero.
+// Species slots per particle the mass arrays hold for S species: the kernels
+// are instantiated for 2, 4 or 8 species and read every slot of their
+// instantiation, so slots S..padded_species(S)-1 are allocated and kept zero.
 inline int padded_species(int S) { return S <= 2 ? 2 : (S <= 4 ? 4 : 8); }
 
 // Pair kernels (one wave per tile).  log2l: lanes per particle = 1 << log2l,
 // or kPrivateLists: one lane per particle with its own candidate rows (tiles
 // of 64 particles).
 constexpr int kPrivateLists = -1;
+// Neighbour cache of the one-lane-per-particle kernels: the row-sum pass keeps
+// every in-cutoff neighbour j != i of a lane (sorted index and weight) for the
+// exchange pass, in a region of kCacheWave entries owned by the lane's wave.
+// A lane with more than kCacheLane neighbours, or whose entries would not fit
+// its wave's region, is marked kCacheMiss and searches its stencil again.
+constexpr int kCacheLane = 8;
+constexpr int kCacheWave = 256;
+constexpr uint32_t kCacheMiss = 15;
 hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
@@ -76,10 +84,10 @@ hipError_t launch_audit_reduce(const double* part, int32_t S1, const int2* chunk
 
 // Full-matrix path of one realisation (binary32 state, bf16-split MFMA).
 struct DenseArgs {
-  const float* pos;        // [dim][cap], sorted
+  const float* pos;        // [cap][PS] particle-major, sorted
   int64_t cap;
   int32_t n;               // particles (one realisation)
-  const float* mass_in;    // [S_pad][cap]
+  const float* mass_in;    // [cap][SP] particle-major
   float* mass_out;
   float* q;                // written by the row-sum pass, read by the exchange
   double* r;

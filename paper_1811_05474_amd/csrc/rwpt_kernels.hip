@@ -4,8 +4,9 @@
 //   scatter, canonical in-cell order) -> row sums r_i -> weights + exchange +
 //   reaction + audit partials -> per-realisation audit.
 //
-// Layout: structure-of-arrays, positions pos[k][cap] and masses mass[s][cap],
-// kept in cell-sorted order; id[p] maps a sorted slot back to the caller's
+// Layout: particle-major, positions pos[PS * p + k] (PS = 1, 2, 4 for 1-, 2-,
+// 3-D: one particle is one aligned vector load) and masses mass[SP * p + s]
+// (SP = 2, 4, 8 species slots, the unused ones zero), kept in cell-sorted order; id[p] maps a sorted slot back to the caller's
 // particle index.  Every reduction runs in a fixed order, so results are
 // bitwise reproducible run to run.
 #include <hip/hip_runtime.h>
@@ -14,6 +15,7 @@
 #include <type_traits>
 
 #include "rwpt_kernels.h"
+#include "rwpt_layout.h"
 
 namespace rwpt {
 
@@ -105,22 +107,6 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return __bui
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 template <typename T, int DIM>
-__device__ __forceinline__ T sep2(const T xi[DIM], const T* __restrict__ pos, int64_t cap, uint32_t j) {
-#pragma clang fp contract(off)
-  const T d0 = pos[j] - xi[0];
-  T s = d0 * d0;
-  if constexpr (DIM > 1) {
-    const T d1 = pos[cap + j] - xi[1];
-    s = fma_t(d1, d1, s);
-  }
-  if constexpr (DIM > 2) {
-    const T d2 = pos[2 * cap + j] - xi[2];
-    s = fma_t(d2, d2, s);
-  }
-  return s;
-}
-
-template <typename T, int DIM>
 __device__ __forceinline__ T sep2v(const T xi[DIM], const T xj[DIM]) {
 #pragma clang fp contract(off)
   const T d0 = xj[0] - xi[0];
@@ -134,6 +120,13 @@ __device__ __forceinline__ T sep2v(const T xi[DIM], const T xj[DIM]) {
     s = fma_t(d2, d2, s);
   }
   return s;
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ T sep2(const T xi[DIM], const T* __restrict__ pos, int64_t j) {
+  T xj[DIM];
+  load_pos<T, DIM>(pos, j, xj);
+  return sep2v<T, DIM>(xi, xj);
 }
 
 // Candidates per lane handled per unrolled block (their loads are issued
@@ -186,8 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_key(
   }
   const RealParams& P = rp[lo];
   T x[DIM];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) x[k] = pos_in[k * cap + p];
+  load_pos<T, DIM>(pos_in, p, x);
   if (do_walk && P.amp > 0.0) {
     T z[3];
     walk_normals<T, DIM>(id[p], seed, *step_ctr, z);
@@ -195,8 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_key(
 #pragma unroll
     for (int k = 0; k < DIM; ++k) x[k] = reflect<T>(x[k] + amp * z[k], (T)P.lo[k], (T)P.hi[k]);
   }
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) pos_out[k * cap + p] = x[k];
+  store_pos<T, DIM>(pos_out, p, x);
   int64_t c = 0;
 #pragma unroll
   for (int k = DIM - 1; k >= 0; --k) {
@@ -343,7 +334,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int32_t n, const uint32_t* _
                                                     uint32_t* __restrict__ tmp_src,
                                                     uint32_t* __restrict__ tmp_id,
                                                     uint32_t* __restrict__ tmp_key) {
-  const int p = blockIdx.x * kBlock + threadIdx.x;
+  // XCD-contiguous ranges: neighbouring particles' gathers and partial-line
+  // writes meet in one L2
+  const int p = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (p >= n) return;
   const uint32_t k = key[p];
   const uint32_t dst = cell_start[k] + slot[p];
@@ -355,24 +348,27 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int32_t n, const uint32_t* _
 // The atomic slot of the scatter depends on arrival order; ranking by the
 // (unique) particle id inside each cell makes the sorted order a function of
 // the positions alone: (cell, id).
-template <typename T, int DIM>
+template <typename T, int DIM, int SMAX>
 __global__ __launch_bounds__(kBlock) void k_canon(
     int32_t n, const uint32_t* __restrict__ tmp_src, const uint32_t* __restrict__ tmp_id,
     const uint32_t* __restrict__ tmp_key, const uint32_t* __restrict__ cell_start,
     const T* __restrict__ pos_in, T* __restrict__ pos_out, int64_t cap, const T* __restrict__ mass_in,
     T* __restrict__ mass_out, int32_t S, uint32_t* __restrict__ id_out, uint32_t* __restrict__ skey) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
+  const int e = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (e >= n) return;
   const uint32_t k = tmp_key[e];
+  const uint32_t src = tmp_src[e];
+  // issue the gathers first; the in-cell ranking below overlaps them
+  T x[DIM], m[SMAX];
+  load_pos<T, DIM>(pos_in, src, x);
+  load_mass<T, SMAX>(mass_in, src, m);  // unused species slots are zero and stay zero
   const uint32_t cs = cell_start[k], ce = cell_start[k + 1];
   const uint32_t my = tmp_id[e];
   uint32_t rank = 0;
   for (uint32_t f = cs; f < ce; ++f) rank += (tmp_id[f] < my) ? 1u : 0u;
   const uint32_t dst = cs + rank;
-  const uint32_t src = tmp_src[e];
-#pragma unroll
-  for (int d = 0; d < DIM; ++d) pos_out[d * cap + dst] = pos_in[d * cap + src];
-  for (int s = 0; s < S; ++s) mass_out[s * cap + dst] = mass_in[s * cap + src];
+  store_pos<T, DIM>(pos_out, dst, x);
+  store_mass<T, SMAX>(mass_out, dst, m);
   id_out[dst] = my;
   skey[dst] = k;
 }
@@ -455,6 +451,67 @@ __device__ __forceinline__ void lane_cell(const RealParams& P, const uint32_t* _
   tl.row = (int)(lk / (uint32_t)P.nc[0]);
 }
 
+// Exchange of a double with lane ^ M: a DPP quad permutation for M = 1, 2
+// (no LDS traffic), a cross-lane permute otherwise.
+template <int M>
+__device__ __forceinline__ double xor_shfl(double v) {
+  if constexpr (M == 1 || M == 2) {
+    constexpr int ctrl = M == 1 ? 0xB1 : 0x4E;  // quad_perm [1,0,3,2] / [2,3,0,1]
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, ctrl, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), ctrl, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+  } else {
+    return __shfl_xor(v, M);
+  }
+}
+
+// Sum of NV values over each aligned group of G lanes by recursive halving (a
+// reduce-scatter): at step M every lane keeps one half of its values, adds the
+// partner's (lane ^ M) copy of that half, and hands over the other half, so
+// the number of values exchanged halves at every step; once one value is
+// left, the remaining steps add it up plainly.  On return v[0 .. NK) holds the
+// group totals of values idx .. idx + NK - 1, and lanes that differ only in
+// the bits above the first NB (the halving steps) hold the same totals.  An
+// upper half shorter than the lower one is padded with zeros; `real` counts
+// the lane's values that are not padding (only those may be written out).
+constexpr int halved_count(int n, int g) {
+  for (int m = 1; m < g && n > 1; m <<= 1) n = (n + 1) / 2;
+  return n;
+}
+constexpr int halving_bits(int n, int g) {
+  int b = 0;
+  for (int m = 1; m < g && n > 1; m <<= 1) {
+    n = (n + 1) / 2;
+    ++b;
+  }
+  return b;
+}
+
+template <int M, int G, int N, int NV>
+__device__ __forceinline__ void halve_sum(double (&v)[NV], int& idx, int& real, int lane) {
+  if constexpr (M < G) {
+    if constexpr (N > 1) {
+      constexpr int H = (N + 1) / 2;
+      const bool up = (lane & M) != 0;
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        double hi = 0.0;
+        if (k + H < N) hi = v[k + H];
+        const double keep = up ? hi : v[k];
+        const double send = up ? v[k] : hi;
+        v[k] = keep + xor_shfl<M>(send);
+      }
+      idx += up ? H : 0;
+      real = up ? (real > H ? real - H : 0) : (real < H ? real : H);
+      halve_sum<M * 2, G, H, NV>(v, idx, real, lane);
+    } else {
+      v[0] += xor_shfl<M>(v[0]);
+      halve_sum<M * 2, G, 1, NV>(v, idx, real, lane);
+    }
+  }
+}
+
 // After the lane reductions: new masses (Eq. 6), reaction, and the tile's
 // audit partials.  `writer` lanes (one per particle) hold acc / racc; lanes
 // 0..G-1 are the writers' first copies, so the audit is reduced over them.
@@ -489,27 +546,34 @@ __device__ __forceinline__ void exchange_epilogue(const RealParams& P, bool sym,
         }
     }
     double va = 0.0, vb = 0.0;
+    T out[SMAX];
 #pragma unroll
-    for (int s = 0; s < SMAX; ++s)
-      if (s < S) {
-        const T v = (T)Mn[s];
-        mout[s * cap + i] = v;
-        tot[s] = (double)v;
-        if (s == react_a) va = (double)v;
-        if (s == react_b) vb = (double)v;
-      }
+    for (int s = 0; s < SMAX; ++s) {
+      out[s] = s < S ? (T)Mn[s] : (T)0;  // unused species slots stay zero
+      tot[s] = (double)out[s];
+      if (s == react_a) va = tot[s];
+      if (s == react_b) vb = tot[s];
+    }
+    store_mass<T, SMAX>(mout, i, out);
     tot[SMAX] = va - vb;
   }
-#pragma unroll
-  for (int off = 1; off < G; off <<= 1) {
-#pragma unroll
-    for (int s = 0; s <= SMAX; ++s) tot[s] += __shfl_xor(tot[s], off);
-  }
-  if ((threadIdx.x & 63) == 0) {
+  // totals over lanes 0..G-1 (the other lanes hold zeros and are reduced
+  // among themselves); value SMAX is sum(A - B)
+  constexpr int NV = SMAX + 1, NK = halved_count(NV, G), NB = halving_bits(NV, G);
+  const int lane = threadIdx.x & 63;
+  int idx = 0, real = NV;
+  halve_sum<1, G, NV, NV>(tot, idx, real, lane);
+  if (lane < (1 << NB)) {
     const int t = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
     double* part = audit_part + (int64_t)t * (S + 1);
-    for (int s = 0; s < S; ++s) part[s] = tot[s < SMAX ? s : 0];
-    part[S] = tot[SMAX];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int vi = idx + k;
+      if (k < real) {
+        if (vi < S) part[vi] = tot[k];
+        else if (vi == SMAX) part[S] = tot[k];
+      }
+    }
   }
 }
 
@@ -529,8 +593,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(
   const RealParams& P = rp[tile.real];
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   T xi[DIM];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  load_pos<T, DIM>(pos, ii, xi);
   lane_cell<T, DIM>(P, skey, ii, tl);
   const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
   double acc = 0.0;
@@ -546,8 +609,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(
           T xj[kUnroll][DIM];
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) xj[u][k] = pos[k * cap + j + u * L];
+            load_pos<T, DIM>(pos, j + u * L, xj[u]);
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
             const T s2 = sep2v<T, DIM>(xi, xj[u]);
@@ -559,7 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(
         accr = (T)0;
       }
       for (; j < je; j += L) {
-        const T s2 = sep2<T, DIM>(xi, pos, cap, j);
+        const T s2 = sep2<T, DIM>(xi, pos, j);
         const T w = kweight(s2, esc);
         accr += (act && s2 <= rc2) ? w : (T)0;
       }
@@ -595,11 +657,9 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
   const RealParams& P = rp[tile.real];
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   T xi[DIM];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  load_pos<T, DIM>(pos, ii, xi);
   T Mi[SMAX];
-#pragma unroll
-  for (int s = 0; s < SMAX; ++s) Mi[s] = min_[s * cap + ii];
+  load_mass<T, SMAX>(min_, ii, Mi);
   lane_cell<T, DIM>(P, skey, ii, tl);
   const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
   double acc[SMAX];
@@ -631,11 +691,9 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
             T xj[kUnroll][DIM], qj[kUnroll], mj[kUnroll][SMAX];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-#pragma unroll
-              for (int k = 0; k < DIM; ++k) xj[u][k] = pos[k * cap + j + u * L];
+              load_pos<T, DIM>(pos, j + u * L, xj[u]);
               qj[u] = q[j + u * L];
-#pragma unroll
-              for (int s = 0; s < SMAX; ++s) mj[u][s] = min_[s * cap + j + u * L];
+              load_mass<T, SMAX>(min_, j + u * L, mj[u]);
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) eval(xj[u], qj[u], mj[u]);
@@ -648,10 +706,8 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
         }
         for (; j < je; j += L) {
           T xj[DIM], mj[SMAX];
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) xj[k] = pos[k * cap + j];
-#pragma unroll
-          for (int s = 0; s < SMAX; ++s) mj[s] = min_[s * cap + j];
+          load_pos<T, DIM>(pos, j, xj);
+          load_mass<T, SMAX>(min_, j, mj);
           eval(xj, q[j], mj);
         }
 #pragma unroll
@@ -679,10 +735,8 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
             T xj[kUnroll][DIM], mj[kUnroll][SMAX];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
-#pragma unroll
-              for (int k = 0; k < DIM; ++k) xj[u][k] = pos[k * cap + j + u * L];
-#pragma unroll
-              for (int s = 0; s < SMAX; ++s) mj[u][s] = min_[s * cap + j + u * L];
+              load_pos<T, DIM>(pos, j + u * L, xj[u]);
+              load_mass<T, SMAX>(min_, j + u * L, mj[u]);
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) eval(xj[u], mj[u]);
@@ -697,10 +751,8 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
         }
         for (; j < je; j += L) {
           T xj[DIM], mj[SMAX];
-#pragma unroll
-          for (int k = 0; k < DIM; ++k) xj[k] = pos[k * cap + j];
-#pragma unroll
-          for (int s = 0; s < SMAX; ++s) mj[s] = min_[s * cap + j];
+          load_pos<T, DIM>(pos, j, xj);
+          load_mass<T, SMAX>(min_, j, mj);
           eval(xj, mj);
         }
 #pragma unroll
@@ -843,16 +895,14 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
   const RealParams& P = rp[tile.real];
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   float xi[DIM];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  load_pos<float, DIM>(pos, ii, xi);
   lane_cell<float, DIM>(P, skey, ii, tl);
   const float rc2 = P.rc2_f, esc = P.escale_f;
   double acc = 0.0;
   if (P.active) {
     for_tile_chunks(P, st, cell_start, tl, tile.begin, [&](int32_t j, bool has, bool act) {
       float xj[DIM];
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) xj[k] = pos[k * cap + j];
+      load_pos<float, DIM>(pos, j, xj);
       if (!has) xj[0] = 3.0e38f;  // s^2 overflows to +inf: outside the cutoff, weight 0
       float a = 0.0f;
       Steps<0, 16>::run([&](auto kc) {
@@ -898,11 +948,9 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
   const RealParams& P = rp[tile.real];
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   float xi[DIM];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  load_pos<float, DIM>(pos, ii, xi);
   float Mi[SMAX];
-#pragma unroll
-  for (int s = 0; s < SMAX; ++s) Mi[s] = min_[s * cap + ii];
+  load_mass<float, SMAX>(min_, ii, Mi);
   lane_cell<float, DIM>(P, skey, ii, tl);
   const float rc2 = P.rc2_f, esc = P.escale_f;
   double acc[SMAX];
@@ -914,13 +962,11 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
   if (P.active) {
     for_tile_chunks(P, st, cell_start, tl, tile.begin, [&](int32_t j, bool has, bool act) {
       float xj[DIM], mj[SMAX];
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) xj[k] = pos[k * cap + j];
+      load_pos<float, DIM>(pos, j, xj);
       if (!has) xj[0] = 3.0e38f;  // outside the cutoff, weight 0
       const float qj = q[j];
       // species rows S..SMAX-1 exist and hold zeros, so no guard is needed
-#pragma unroll
-      for (int s = 0; s < SMAX; ++s) mj[s] = min_[s * cap + j];
+      load_mass<float, SMAX>(min_, j, mj);
       float accr[SMAX];
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) accr[s] = 0.0f;
@@ -1004,57 +1050,167 @@ __device__ __forceinline__ void for_own_rows(const RealParams& P, const StencilR
   }
 }
 
+// Tile (wave) index of the calling wave, as tile_lane_setup derives it.
+__device__ __forceinline__ int64_t wave_tile() {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  return (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + wave;
+}
+
+// Row-sum pass of the one-lane-per-particle kernels.  Each lane takes the
+// cells its own cutoff box [x - r, x + r]^d overlaps (r the geometric cutoff,
+// cells by the same monotone map as the cell keys, so no neighbour is
+// missed): per axis a cell range, hence (y, z) rows of one contiguous x-range
+// each.  Rows are taken kRowBatch at a time: all their cell ranges are loaded
+// first, then the concatenated candidate list is walked kCandBatch candidates
+// per iteration with all their loads in flight.  Candidate t of the
+// concatenation is j = t + delta[q] for the last row q whose first flat index
+// off[q] is <= t.
+template <int DIM>
+struct PrivBatch {
+  static constexpr int kRowBatch = DIM == 1 ? 1 : 4;
+  static constexpr int kCandBatch = 4;
+};
+
+// Cell coordinate of coordinate value v along axis k (as the cell keys map it).
+// Clamped in floating point first, so that an infinite cutoff (v = +-inf)
+// converts safely.
+__device__ __forceinline__ int cell_of(const RealParams& P, int k, double v) {
+  double u = floor((v - P.lo[k]) * P.inv_h[k]);
+  u = u < 0.0 ? 0.0 : u;
+  u = u > (double)(P.nc[k] - 1) ? (double)(P.nc[k] - 1) : u;
+  return (int)u;
+}
+
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_rowsum_priv(
     const T* __restrict__ pos, const int64_t cap, const uint32_t* __restrict__ skey,
     const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles, const int32_t ntiles,
     const RealParams* __restrict__ rp, const StencilRow* __restrict__ st, double* __restrict__ r_out,
-    T* __restrict__ q_out) {
-  TileLane tl;
-  Tile tile;
-  if (!tile_lane_setup<0>(tiles, ntiles, tl, tile)) return;
-  const RealParams& P = rp[tile.real];
-  if (!tl.valid) return;
-  T xi[DIM];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + tl.i];
-  const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
-  double acc = 1.0;  // only the self weight when the transfer is off
-  if (P.active) {
-    acc = 0.0;
-    for_own_rows<T, DIM>(P, st, cell_start, skey[tl.i] - (uint32_t)P.cell_off, [&](uint32_t jb, uint32_t je) {
-      T a = (T)0;
-      for (uint32_t j = jb; j < je; ++j) {
-        const T s2 = sep2<T, DIM>(xi, pos, cap, j);
-        const T w = kweight(s2, esc);
-        a += s2 <= rc2 ? w : (T)0;
-      }
-      acc += (double)a;
-    });
-  }
-  r_out[tl.i] = acc;
-  q_out[tl.i] = (T)(1.0 / acc);
-}
-
-template <typename T, int DIM, int SMAX>
-__global__ __launch_bounds__(kBlock) void k_exchange_priv(
-    const T* __restrict__ pos, const int64_t cap, const T* __restrict__ min_, T* __restrict__ mout,
-    const T* __restrict__ q, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ cell_start,
-    const Tile* __restrict__ tiles, const int32_t ntiles, const RealParams* __restrict__ rp,
-    const StencilRow* __restrict__ st, const int32_t S, const int32_t react_a, const int32_t react_b,
-    const int32_t norm, double* __restrict__ audit_part) {
+    T* __restrict__ q_out, uint16_t* __restrict__ nb_meta, uint32_t* __restrict__ nb_idx,
+    T* __restrict__ nb_w) {
+  constexpr int RB = PrivBatch<DIM>::kRowBatch, CB = PrivBatch<DIM>::kCandBatch;
   TileLane tl;
   Tile tile;
   if (!tile_lane_setup<0>(tiles, ntiles, tl, tile)) return;
   const RealParams& P = rp[tile.real];
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   T xi[DIM];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
-  T Mi[SMAX];
-#pragma unroll
-  for (int s = 0; s < SMAX; ++s) Mi[s] = min_[s * cap + ii];
+  load_pos<T, DIM>(pos, ii, xi);
   const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
+  double acc = 1.0;  // only the self weight when the transfer is off
+  // the lane's cached neighbours, slot-major per wave: [slot][lane]
+  __shared__ uint32_t sh_j[kBlock / 64][kCacheLane * 64];
+  __shared__ T sh_w[kBlock / 64][kCacheLane * 64];
+  const int lane = threadIdx.x & 63;
+  uint32_t* const lj = &sh_j[threadIdx.x >> 6][lane];
+  T* const lw = &sh_w[threadIdx.x >> 6][lane];
+  uint32_t cnt = 0;
+  if (P.active && tl.valid) {
+    acc = 0.0;
+    const double rg = P.rc_geo;
+    int ca[3] = {0, 0, 0}, cb_[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      ca[k] = cell_of(P, k, (double)xi[k] - rg);
+      cb_[k] = cell_of(P, k, (double)xi[k] + rg);
+    }
+    const int nyr = cb_[1] - ca[1] + 1;
+    const int nrows = nyr * (cb_[2] - ca[2] + 1);
+    const uint32_t nc0 = (uint32_t)P.nc[0], nc1 = (uint32_t)P.nc[1];
+    const uint32_t coff = (uint32_t)P.cell_off;
+    int yy = ca[1], zz = ca[2];
+    for (int r0 = 0; r0 < nrows; r0 += RB) {
+      uint32_t off[RB];
+      int32_t delta[RB];
+      uint32_t total = 0;
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        const bool in = r0 + q < nrows;
+        const uint32_t base = coff + ((uint32_t)zz * nc1 + (uint32_t)yy) * nc0;
+        const uint32_t jb = cell_start[base + (uint32_t)ca[0]];
+        const uint32_t je = cell_start[base + (uint32_t)cb_[0] + 1u];
+        off[q] = total;
+        delta[q] = (int32_t)jb - (int32_t)total;
+        total += in ? je - jb : 0u;
+        // next row: y fastest; past the last row (yy, zz) stays a valid cell
+        const bool wrap = yy == cb_[1];
+        const bool last = wrap && zz == cb_[2];
+        yy = last ? yy : (wrap ? ca[1] : yy + 1);
+        zz = last ? zz : (wrap ? zz + 1 : zz);
+      }
+      for (uint32_t t0 = 0; t0 < total; t0 += CB) {
+        uint32_t jv[CB];
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+          const uint32_t t = t0 + u;
+          int32_t d = delta[0];
+#pragma unroll
+          for (int q = 1; q < RB; ++q) d = t >= off[q] ? delta[q] : d;
+          jv[u] = t < total ? (uint32_t)((int32_t)t + d) : (uint32_t)ii;
+        }
+        T xj[CB][DIM];
+#pragma unroll
+        for (int u = 0; u < CB; ++u) load_pos<T, DIM>(pos, jv[u], xj[u]);
+        T a = (T)0;
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+          const T s2 = sep2v<T, DIM>(xi, xj[u]);
+          const T w = kweight(s2, esc);
+          const bool hit = t0 + u < total && s2 <= rc2;
+          a += hit ? w : (T)0;
+          if (hit && jv[u] != (uint32_t)ii && cnt <= (uint32_t)kCacheLane) {
+            if (cnt < (uint32_t)kCacheLane) {
+              lj[cnt * 64] = jv[u];
+              lw[cnt * 64] = w;
+            }
+            ++cnt;
+          }
+        }
+        acc += (double)a;
+      }
+    }
+  }
+  // wave-exclusive prefix of the kept counts (each at most kCacheLane < 16)
+  const uint32_t keep = cnt <= (uint32_t)kCacheLane ? cnt : 0u;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  uint32_t off = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) off += (uint32_t)__popcll(__ballot((keep >> b) & 1u) & below) << b;
+  if (!tl.valid) return;
+  r_out[ii] = acc;
+  q_out[ii] = (T)(1.0 / acc);
+  const bool miss = cnt > (uint32_t)kCacheLane || off + keep > (uint32_t)kCacheWave;
+  if (!miss) {
+    const int64_t e0 = wave_tile() * kCacheWave + off;
+#pragma unroll
+    for (int k = 0; k < kCacheLane; ++k)
+      if ((uint32_t)k < keep) {
+        nb_idx[e0 + k] = lj[k * 64];
+        nb_w[e0 + k] = lw[k * 64];
+      }
+  }
+  nb_meta[ii] = miss ? (uint16_t)kCacheMiss : (uint16_t)(keep ? ((off << 4) | keep) : 0u);
+}
+
+// Exchange with the row-sum pass's neighbour cache: a cached lane reads its
+// neighbours' indices and weights (no positions, no search); a lane marked as
+// a miss walks its stencil rows as the row-sum pass did.  r_i for the row
+// normalisation comes from the row-sum pass.
+template <typename T, int DIM, int SMAX>
+__global__ __launch_bounds__(kBlock) void k_exchange_priv(
+    const T* __restrict__ pos, const int64_t cap, const T* __restrict__ min_, T* __restrict__ mout,
+    const T* __restrict__ q, const double* __restrict__ r_in, const uint32_t* __restrict__ skey,
+    const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles, const int32_t ntiles,
+    const RealParams* __restrict__ rp, const StencilRow* __restrict__ st, const int32_t S,
+    const int32_t react_a, const int32_t react_b, const int32_t norm, double* __restrict__ audit_part,
+    const uint16_t* __restrict__ nb_meta, const uint32_t* __restrict__ nb_idx, const T* __restrict__ nb_w) {
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<0>(tiles, ntiles, tl, tile)) return;
+  const RealParams& P = rp[tile.real];
+  const int32_t ii = tl.valid ? tl.i : tile.end - 1;
+  T Mi[SMAX];
+  load_mass<T, SMAX>(min_, ii, Mi);
   double acc[SMAX];
 #pragma unroll
   for (int s = 0; s < SMAX; ++s) acc[s] = 0.0;
@@ -1062,25 +1218,62 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
   const bool sym = (norm == 0);
   if (P.active && tl.valid) {
     const T qi = q[ii];
-    for_own_rows<T, DIM>(P, st, cell_start, skey[ii] - (uint32_t)P.cell_off, [&](uint32_t jb, uint32_t je) {
-      T accr[SMAX];
+    const uint32_t meta = nb_meta[ii];
+    if ((meta & 15u) != kCacheMiss) {
+      racc = r_in[ii];
+      const uint32_t c = meta & 15u;
+      const int64_t e0 = wave_tile() * kCacheWave + (meta >> 4);
+      // neighbours NB at a time, all their loads in flight together
+      constexpr int NB = SMAX * sizeof(T) <= 16 ? 4 : 2;
+      for (uint32_t k0 = 0; k0 < c; k0 += NB) {
+        uint32_t jv[NB];
+        T wv[NB];
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) accr[s] = (T)0;
-      T rr = (T)0;
-      for (uint32_t j = jb; j < je; ++j) {
-        const T s2 = sep2<T, DIM>(xi, pos, cap, j);
-        if (!(s2 <= rc2)) continue;  // sparse: most candidates miss, skip their loads
-        const T w = kweight(s2, esc);
-        // species rows S..SMAX-1 exist and hold zeros
-        const T p = sym ? w * (qi + q[j]) : w;
-        rr += w;
+        for (int u = 0; u < NB; ++u) {
+          const bool ok = k0 + u < c;
+          const int64_t e = e0 + (ok ? k0 + u : 0);
+          jv[u] = ok ? nb_idx[e] : (uint32_t)ii;
+          wv[u] = ok ? nb_w[e] : (T)0;
+        }
+        T qj[NB], Mj[NB][SMAX];
 #pragma unroll
-        for (int s = 0; s < SMAX; ++s) accr[s] += p * (min_[s * cap + j] - Mi[s]);
+        for (int u = 0; u < NB; ++u) {
+          qj[u] = q[jv[u]];
+          load_mass<T, SMAX>(min_, jv[u], Mj[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+          const T p = sym ? wv[u] * (qi + qj[u]) : wv[u];  // 0 past the lane's count
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s) acc[s] += (double)(p * (Mj[u][s] - Mi[s]));
+        }
       }
+    } else {
+      T xi[DIM];
+      load_pos<T, DIM>(pos, ii, xi);
+      const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
+      for_own_rows<T, DIM>(P, st, cell_start, skey[ii] - (uint32_t)P.cell_off, [&](uint32_t jb, uint32_t je) {
+        T accr[SMAX];
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
-      racc += (double)rr;
-    });
+        for (int s = 0; s < SMAX; ++s) accr[s] = (T)0;
+        T rr = (T)0;
+        for (uint32_t j = jb; j < je; ++j) {
+          const T s2 = sep2<T, DIM>(xi, pos, j);
+          if (!(s2 <= rc2)) continue;  // sparse: most candidates miss, skip their loads
+          const T w = kweight(s2, esc);
+          // species rows S..SMAX-1 exist and hold zeros
+          const T p = sym ? w * (qi + q[j]) : w;
+          rr += w;
+          T mj[SMAX];
+          load_mass<T, SMAX>(min_, j, mj);
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s) accr[s] += p * (mj[s] - Mi[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
+        racc += (double)rr;
+      });
+    }
   }
   exchange_epilogue<T, SMAX, 64>(P, sym, acc, racc, Mi, tl.valid, tl.i, mout, cap, S, react_a, react_b,
                                  audit_part);
@@ -1098,8 +1291,7 @@ __global__ __launch_bounds__(kBlock) void k_count(PairArgs a) {
   const int64_t cap = a.cap;
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   T xi[DIM];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  load_pos<T, DIM>(pos, ii, xi);
   const uint32_t lk = a.skey[ii] - (uint32_t)P.cell_off;
   tl.cx = (int)(lk % (uint32_t)P.nc[0]);
   tl.row = (int)(lk / (uint32_t)P.nc[0]);
@@ -1110,7 +1302,7 @@ __global__ __launch_bounds__(kBlock) void k_count(PairArgs a) {
       const uint32_t len = je - jb, nfull = len >> LOG2L, rem = len & (L - 1);
       uint32_t j = jb + tl.gl;
       auto body = [&](uint32_t jj) {
-        const T s2 = sep2<T, DIM>(xi, pos, cap, jj);
+        const T s2 = sep2<T, DIM>(xi, pos, jj);
         if (act) {
           ++evals;
           if (s2 <= rc2 && jj != (uint32_t)tl.i) ++pairs;
@@ -1145,8 +1337,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr(PairArgs a) {
   const int64_t cap = a.cap;
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   T xi[DIM];
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) xi[k] = pos[k * cap + ii];
+  load_pos<T, DIM>(pos, ii, xi);
   const uint32_t lk = a.skey[ii] - (uint32_t)P.cell_off;
   tl.cx = (int)(lk % (uint32_t)P.nc[0]);
   tl.row = (int)(lk / (uint32_t)P.nc[0]);
@@ -1168,7 +1359,7 @@ __global__ __launch_bounds__(kBlock) void k_nbr(PairArgs a) {
     const uint32_t len = je - jb, nfull = len >> LOG2L, rem = len & (L - 1);
     uint32_t j = jb + tl.gl;
     auto body = [&](uint32_t jj) {
-      const T s2 = sep2<T, DIM>(xi, pos, cap, jj);
+      const T s2 = sep2<T, DIM>(xi, pos, jj);
       if (act && s2 <= rc2) {
         const uint32_t at = atomicAdd(&a.nbr_cursor[tl.i], 1u);
         if (FILL) {
@@ -1302,7 +1493,13 @@ hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
   if (n <= 0) return hipSuccess;
   const dim3 g(blocks_for(n)), b(kBlock);
 #define RWPT_CN(T, D)                                                                           \
-  hipLaunchKernelGGL((k_canon<T, D>), g, b, 0, s, n, tmp_src, tmp_id, tmp_key, cell_start,        \
+  do {                                                                                          \
+    if (S <= 2) RWPT_CN1(T, D, 2);                                                              \
+    else if (S <= 4) RWPT_CN1(T, D, 4);                                                         \
+    else RWPT_CN1(T, D, 8);                                                                     \
+  } while (0)
+#define RWPT_CN1(T, D, SM)                                                                      \
+  hipLaunchKernelGGL((k_canon<T, D, SM>), g, b, 0, s, n, tmp_src, tmp_id, tmp_key, cell_start,    \
                      (const T*)pos_in, (T*)pos_out, cap, (const T*)mass_in, (T*)mass_out, S, id_out, \
                      skey)
   if (fp64) {
@@ -1314,6 +1511,7 @@ hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
     else if (dim == 2) RWPT_CN(float, 2);
     else RWPT_CN(float, 3);
   }
+#undef RWPT_CN1
 #undef RWPT_CN
   return hipGetLastError();
 }
@@ -1356,7 +1554,8 @@ hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStr
     return dispatch_tdl(fp64, dim, 0, [&](auto t, auto d, auto) {
       using T = decltype(t);
       hipLaunchKernelGGL((k_rowsum_priv<T, decltype(d)::value>), g, b, 0, s, (const T*)a.pos, a.cap, a.skey,
-                         a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (T*)a.q_out);
+                         a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (T*)a.q_out, a.nb_meta,
+                         a.nb_idx, (T*)a.nb_w);
     });
   }
   if (!fp64 && log2l == 2) {
@@ -1386,8 +1585,9 @@ hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipS
       using T = decltype(t);
       constexpr int D = decltype(d)::value;
 #define RWPT_EXP_ARGS                                                                                  \
-  (const T*)a.pos, a.cap, (const T*)a.mass_in, (T*)a.mass_out, (const T*)a.q_in, a.skey, a.cell_start,   \
-      a.tiles, a.ntiles, a.rp, a.st, a.S, a.react_a, a.react_b, a.norm, a.audit_part
+  (const T*)a.pos, a.cap, (const T*)a.mass_in, (T*)a.mass_out, (const T*)a.q_in, a.r_out, a.skey,        \
+      a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.S, a.react_a, a.react_b, a.norm, a.audit_part,      \
+      a.nb_meta, a.nb_idx, (const T*)a.nb_w
       if (a.S <= 2) hipLaunchKernelGGL((k_exchange_priv<T, D, 2>), g, b, 0, s, RWPT_EXP_ARGS);
       else if (a.S <= 4) hipLaunchKernelGGL((k_exchange_priv<T, D, 4>), g, b, 0, s, RWPT_EXP_ARGS);
       else hipLaunchKernelGGL((k_exchange_priv<T, D, 8>), g, b, 0, s, RWPT_EXP_ARGS);

@@ -536,3 +536,38 @@ def test_interface1d_l50_matches_erfc(prec):
     assert math.sqrt(np.mean((prof - ex_mid) ** 2)) < 0.004
     assert np.abs(prof - ex_mid).max() < 0.012
     ens.close()
+
+
+# ------------------------------------- one lane per particle, neighbour cache ----
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+@pytest.mark.parametrize("mean_nb", [0.7, 2.5, 6.0, 12.0])
+@pytest.mark.parametrize("prec,tol,norm", [(F32, 1e-5, rwpt.RWPT_NORM_SYM), (F64, 1e-12, rwpt.RWPT_NORM_ROW)])
+def test_private_lists_cached_and_missed_neighbours(dim, mean_nb, prec, tol, norm):
+    # mean in-cutoff neighbours per particle from 0.7 (every lane cached) to 12
+    # (most lanes above the per-lane limit of 8, waves beyond their region):
+    # cached lanes, missed lanes and mixed waves must all match the oracle
+    n, dt, seed = 20000, 0.1, 7000 + dim
+    unit = {1: 2.0, 2: math.pi, 3: 4.0 * math.pi / 3.0}[dim]
+    rc = (mean_nb / ((n - 1) * unit)) ** (1.0 / dim)
+    D = rc * rc / (72.0 * dt)
+    x = W.positions(n, dim, seed)
+    M = W.masses(n, 2, seed)
+    if prec == F32:
+        x, M = f32(x), f32(M)
+    lo, hi = (0.0,) * dim, (1.0,) * dim
+    ens = make(dim=dim, rw=1.0, prec=prec, norm=norm, seed=seed, lanes=-1)
+    ens.init([n], x, M)
+    mcur, xcur = M, x
+    onorm = oracle.NORM_SYM if norm == rwpt.RWPT_NORM_SYM else oracle.NORM_ROW
+    for step in range(2):
+        ens.step(dt, D, 1)
+        pos, got = ens.positions(), ens.masses()
+        walked = oracle.walk(xcur, np.arange(n), seed, step, D, dt, lo, hi)
+        assert np.abs(pos - walked).max() < (2e-6 if prec == F32 else 1e-12)
+        ref = oracle.transfer(pos, mcur, D, dt, kappa=3.0, norm=onorm, prec=32 if prec == F32 else 64)
+        assert normerr(got, ref) < tol, (step, normerr(got, ref))
+        mcur, xcur = got, pos
+    pairs, _ = ens.count_pairs(dt, D)
+    assert 0.5 * mean_nb * n < pairs < 1.5 * mean_nb * n
+    ens.close()
