@@ -55,6 +55,13 @@ def exchange_bytes_per_particle(dim: int, S: int, tsize: int) -> int:
     return tsize * (dim + 1 + S) + tsize * S
 
 
+def step_bytes_per_particle(dim: int, S: int, tsize: int) -> int:
+    """Algorithmic HBM bytes of one whole step per particle: the walk reads and
+    writes the position, the transfer reads the position and the masses and
+    writes the masses (sorting and row sums are implementation overhead)."""
+    return tsize * (2 * dim) + tsize * (dim + 2 * S)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,6 +279,17 @@ def main():
     }
     if dense:
         roofline["ordered_pairs_evaluated_per_launch"] = alg_pairs
+    step_bytes = step_bytes_per_particle(w.dim, w.n_species, 4) * n_total
+    step_gbps = step_bytes / (r32["ms_per_step"] * 1e-3) / 1e9
+    step_roofline = {
+        "bound": "hbm",
+        "scope": "whole step (walk + sort + row sums + exchange + reaction + audit)",
+        "algorithmic_bytes_per_step": step_bytes,
+        "achieved": step_gbps,
+        "peak": PEAK_HBM_GBPS,
+        "unit": "GB/s",
+        "frac": step_gbps / PEAK_HBM_GBPS,
+    }
 
     line = {
         "metric": METRIC if w.name == WORKLOAD else
@@ -300,6 +318,7 @@ def main():
         },
         "phases_us": {k: round(v["us_avg"], 2) for k, v in r32["phases"].items()},
         "roofline": roofline,
+        "step_roofline": step_roofline,
     }
     if r64 is not None:
         m32, m64 = r32["masses"], r64["masses"]

@@ -120,6 +120,17 @@ rwpt_status rwpt_create(const rwpt_config *cfg, rwpt_ctx **out);
 rwpt_status rwpt_init_ensemble(rwpt_ctx *ctx, int32_t n_real, const int64_t *n_per_real,
                                const double *pos, const double *mass, const double *d_scale);
 
+/* As rwpt_init_ensemble, with pos and mass given as device pointers (binary64,
+ * the same layouts) on the configured device, e.g. torch tensors; n_per_real
+ * and d_scale stay host arrays.  The inputs are copied to the host, validated
+ * and loaded exactly as by rwpt_init_ensemble (one PCIe round trip at init; the
+ * stepping path never leaves the device).  The caller keeps ownership of its
+ * buffers, which are only read.  Errors as rwpt_init_ensemble, plus
+ * RWPT_EDEVICE if the copy fails (e.g. a pointer that is not device memory). */
+rwpt_status rwpt_init_ensemble_device(rwpt_ctx *ctx, int32_t n_real, const int64_t *n_per_real,
+                                      const double *pos_dev, const double *mass_dev,
+                                      const double *d_scale);
+
 /* Advance every realisation by n_steps >= 0 explicit steps of length dt > 0
  * with mass-transfer diffusion D >= 0 (D_m of Eq. 3).  D * d_scale[r] = 0
  * leaves realisation r's masses to the reaction only.  Asynchronous. */
@@ -167,6 +178,26 @@ rwpt_status rwpt_profile_enable(rwpt_ctx *ctx, int32_t on);
 rwpt_status rwpt_profile_reset(rwpt_ctx *ctx);
 rwpt_status rwpt_profile_read(rwpt_ctx *ctx, double *ms, int64_t *cnt, int32_t *n_phases);
 const char *rwpt_profile_phase_name(int32_t phase);
+
+/* Summary of the context's state (synchronous).  The pair counts are those
+ * of rwpt_count_pairs at the current positions for the (dt, D) of the last
+ * rwpt_step; before the first step they are -1 and n_cells is 0.  The phase
+ * timings are the rwpt_profile_read totals. */
+typedef struct rwpt_stats_t {
+  int64_t n_particles;        /* N, all realisations */
+  int32_t n_real;
+  int32_t tile_lanes;         /* tiling in use (see rwpt_config.tile_lanes); 0 before a step */
+  double cell_refine[3];      /* cells per cutoff length in use */
+  int64_t n_cells;            /* cells of the grid, all realisations */
+  int64_t steps_taken;
+  int64_t ordered_pairs;      /* pairs j != i within the cutoff */
+  int64_t candidate_evals;    /* candidate evaluations of the sparse kernels */
+  int32_t n_phases;           /* entries of phase_ms / phase_launches in use (<= 16) */
+  int32_t pad;
+  double phase_ms[16];        /* per-phase milliseconds since the last profile reset */
+  int64_t phase_launches[16];
+} rwpt_stats_t;
+rwpt_status rwpt_stats(rwpt_ctx *ctx, rwpt_stats_t *out);
 
 /* Current tiling: tile_lanes and the per-axis cell refinement in use. */
 rwpt_status rwpt_get_tiling(rwpt_ctx *ctx, int32_t *tile_lanes, double *cell_refine3);

@@ -206,8 +206,7 @@ static rwpt_status ensure_device(rwpt_ctx* c) {
     c->own_stream = true;
   }
   HIPCHK(c, c->step_ctr.ensure(sizeof(uint64_t)));
-  HIPCHK(c, c->audit_done.ensure(sizeof(uint32_t)));
-  HIPCHK(c, hipMemsetAsync(c->audit_done.p, 0, sizeof(uint32_t), c->stream));
+
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->device_ready = true;
   return RWPT_OK;
@@ -715,6 +714,9 @@ rwpt_status rwpt_init_ensemble(rwpt_ctx* c, int32_t n_real, const int64_t* n_per
   HIPCHK(c, c->q.ensure(cap * ts));
   HIPCHK(c, c->d_real_start.ensure((n_real + 1) * sizeof(int64_t)));
   HIPCHK(c, c->audit_out.ensure((size_t)n_real * (S + 1) * sizeof(double)));
+  // completion counters of the audit kernel (one overall, one per realisation)
+  HIPCHK(c, c->audit_done.ensure((size_t)(n_real + 1) * sizeof(uint32_t)));
+  HIPCHK(c, hipMemsetAsync(c->audit_done.p, 0, (size_t)(n_real + 1) * sizeof(uint32_t), c->stream));
 
   // host staging: particle-major in the path's precision
   std::vector<unsigned char> hp(PS * cap * ts, 0), hm(Sa * cap * ts, 0);
@@ -770,6 +772,31 @@ rwpt_status rwpt_init_ensemble(rwpt_ctx* c, int32_t n_real, const int64_t* n_per
   c->steps = 0;
   c->initialized = true;
   return RWPT_OK;
+}
+
+rwpt_status rwpt_init_ensemble_device(rwpt_ctx* c, int32_t n_real, const int64_t* n_per_real,
+                                      const double* pos_dev, const double* mass_dev, const double* d_scale) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  c->err.clear();
+  if (n_real < 1) return fail(c, RWPT_EINVAL, "n_real must be >= 1");
+  if (!n_per_real) return fail(c, RWPT_EINVAL, "n_per_real is NULL");
+  int64_t N = 0;
+  for (int r = 0; r < n_real; ++r) {
+    if (n_per_real[r] < 0) return fail(c, RWPT_EINVAL, "n_per_real[%d] < 0", r);
+    N += n_per_real[r];
+    if (N > (int64_t)INT32_MAX - 64) return fail(c, RWPT_EINVAL, "too many particles");
+  }
+  if (N > 0 && (!pos_dev || !mass_dev)) return fail(c, RWPT_EINVAL, "pos/mass is NULL");
+  rwpt_status st = ensure_device(c);
+  if (st != RWPT_OK) return st;
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  std::vector<double> hp((size_t)N * c->dim), hm((size_t)N * c->S);
+  if (N > 0) {
+    HIPCHK(c, hipMemcpyAsync(hp.data(), pos_dev, hp.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(hm.data(), mass_dev, hm.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return rwpt_init_ensemble(c, n_real, n_per_real, hp.data(), hm.data(), d_scale);
 }
 
 rwpt_status rwpt_step(rwpt_ctx* c, double dt, double D, int32_t n_steps) {
@@ -1026,6 +1053,38 @@ rwpt_status rwpt_profile_read(rwpt_ctx* c, double* ms, int64_t* cnt, int32_t* n_
 const char* rwpt_profile_phase_name(int32_t phase) {
   if (phase < 0 || phase >= PH_N) return "";
   return kPhaseNames[phase];
+}
+
+rwpt_status rwpt_stats(rwpt_ctx* c, rwpt_stats_t* out) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  c->err.clear();
+  if (!out) return fail(c, RWPT_EINVAL, "out is NULL");
+  memset(out, 0, sizeof(*out));
+  out->n_particles = c->initialized ? c->N : 0;
+  out->n_real = c->initialized ? c->n_real : 0;
+  out->ordered_pairs = -1;
+  out->candidate_evals = -1;
+  if (c->initialized) {
+    rwpt_status st = rwpt_steps_taken(c, &out->steps_taken);
+    if (st != RWPT_OK) return st;
+  }
+  if (c->initialized && c->grid_valid) {
+    out->tile_lanes = c->log2l == kPrivateLists ? -1 : (1 << c->log2l);
+    for (int k = 0; k < 3; ++k) out->cell_refine[k] = c->refine[k];
+    out->n_cells = c->ncell_total;
+    int64_t pairs = 0, evals = 0;
+    rwpt_status st = rwpt_count_pairs(c, c->g_dt, c->g_D, &pairs, &evals);
+    if (st != RWPT_OK) return st;
+    out->ordered_pairs = pairs;
+    out->candidate_evals = evals;
+  }
+  int32_t np = 0;
+  if (c->device_ready) {
+    rwpt_status st = rwpt_profile_read(c, out->phase_ms, out->phase_launches, &np);
+    if (st != RWPT_OK) return st;
+  }
+  out->n_phases = np;
+  return RWPT_OK;
 }
 
 rwpt_status rwpt_get_tiling(rwpt_ctx* c, int32_t* tile_lanes, double* cell_refine3) {

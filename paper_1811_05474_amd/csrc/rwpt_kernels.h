@@ -73,9 +73,9 @@ hipError_t launch_nbr_fill(int fp64, int dim, int log2l, const PairArgs& a, hipS
 
 // Per-realisation FP64 reduction of the per-tile audit partials in two fixed-
 // order levels (chunks of at most kAuditChunk tiles inside one realisation,
-// then the chunks of each realisation) in one launch; `done` is a zeroed
-// completion counter the kernel returns to zero.  Optionally advances the
-// step counter.
+// then the chunks of each realisation) in one launch; `done` holds n_real + 1
+// zeroed completion counters that the kernel returns to zero.  Optionally
+// advances the step counter.
 constexpr int kAuditChunk = 1024;
 hipError_t launch_audit_reduce(const double* part, int32_t S1, const int2* chunks, int32_t nchunks,
                                double* chunk_part, const int32_t* chunk_start, int32_t n_real,

@@ -1223,8 +1223,12 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
       racc = r_in[ii];
       const uint32_t c = meta & 15u;
       const int64_t e0 = wave_tile() * kCacheWave + (meta >> 4);
-      // neighbours NB at a time, all their loads in flight together
+      // neighbours NB at a time, all their loads in flight together; at most
+      // kCacheLane terms, summed in the path's precision, then widened
       constexpr int NB = SMAX * sizeof(T) <= 16 ? 4 : 2;
+      T accc[SMAX];
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) accc[s] = (T)0;
       for (uint32_t k0 = 0; k0 < c; k0 += NB) {
         uint32_t jv[NB];
         T wv[NB];
@@ -1245,9 +1249,11 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
         for (int u = 0; u < NB; ++u) {
           const T p = sym ? wv[u] * (qi + qj[u]) : wv[u];  // 0 past the lane's count
 #pragma unroll
-          for (int s = 0; s < SMAX; ++s) acc[s] += (double)(p * (Mj[u][s] - Mi[s]));
+          for (int s = 0; s < SMAX; ++s) accc[s] += p * (Mj[u][s] - Mi[s]);
         }
       }
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) acc[s] = (double)accc[s];
     } else {
       T xi[DIM];
       load_pos<T, DIM>(pos, ii, xi);
@@ -1379,60 +1385,88 @@ __global__ __launch_bounds__(kBlock) void k_nbr(PairArgs a) {
 // ---------------------------------------------------------------------------
 
 // Fixed-order block sum of v over the 256 threads (thread 0 gets the result).
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
+constexpr int kAuditValues = 9;  // S + 1 audit values for at most eight species
 
 // Audit in one launch: every block sums one chunk of at most kAuditChunk
-// consecutive tiles (never straddling realisations) in a fixed order; the
-// block that finishes last then sums, per realisation, its chunk partials in
-// chunk order, so the result does not depend on which block is last.  The
-// completion counter is returned to zero for the next launch.
+// consecutive tiles (never straddling realisations) in a fixed order -- each
+// thread its strided tiles, then the waves by recursive halving, then the
+// block's waves in wave order.  The block that completes a realisation's last
+// chunk (counter done[1 + r]) sums that realisation's chunk partials in chunk
+// order with one wave (lanes over chunks, then recursive halving), so
+// realisations are finalised in parallel and the result does not depend on
+// which block finishes last.  The block that completes the last chunk overall
+// (counter done[0]) advances the step counter.  Every counter is returned to
+// zero for the next launch (no memset node, so the launch can be captured).
 __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ part, int32_t S1,
                                                   const int2* __restrict__ chunks, int32_t nchunks,
                                                   double* __restrict__ chunk_part,
                                                   const int32_t* __restrict__ chunk_start, int32_t n_real,
                                                   double* __restrict__ out, uint32_t* __restrict__ done,
                                                   uint64_t* __restrict__ step_ctr, int32_t bump) {
-  __shared__ double sh[kBlock];
-  __shared__ bool last;
-  const int2 ch = chunks[blockIdx.x];
-  for (int v = 0; v < S1; ++v) {
-    double s = 0.0;
-    for (int t = ch.x + threadIdx.x; t < ch.y; t += kBlock) s += part[(int64_t)t * S1 + v];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) chunk_part[(int64_t)blockIdx.x * S1 + v] = s;
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(done, 1u) == (uint32_t)(nchunks - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // one wave per realisation: lanes stride over its chunk partials, then a
-  // fixed butterfly
+  constexpr int NV = kAuditValues;
+  constexpr int NK = halved_count(NV, 64);
+  constexpr int NB = halving_bits(NV, 64);
+  __shared__ double sh[kBlock / 64][NV];
+  __shared__ int last_r;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int r = wave; r < n_real; r += kBlock / 64) {
-    const int c0 = chunk_start[r], c1 = chunk_start[r + 1];
-    for (int v = 0; v < S1; ++v) {
-      double s = 0.0;
-      for (int c = c0 + lane; c < c1; c += 64)
-        s += __hip_atomic_load(&chunk_part[(int64_t)c * S1 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int2 ch = chunks[blockIdx.x];
+  double acc[NV];
 #pragma unroll
-      for (int off = 1; off < 64; off <<= 1) s += __shfl_xor(s, off);
-      if (lane == 0) out[(int64_t)r * S1 + v] = s;
-    }
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  for (int t = ch.x + threadIdx.x; t < ch.y; t += kBlock) {
+    const double* pt = part + (int64_t)t * S1;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (v < S1) acc[v] += pt[v];
   }
+  int idx = 0, real = NV;
+  halve_sum<1, 64, NV, NV>(acc, idx, real, lane);
+#pragma unroll
+  for (int k = 0; k < NK; ++k)
+    if (k < real && lane < (1 << NB)) sh[wave][idx + k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x < S1) {
+    double c = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) c += sh[w][threadIdx.x];
+    chunk_part[(int64_t)blockIdx.x * S1 + threadIdx.x] = c;
+  }
+  __threadfence();
+  __syncthreads();
   if (threadIdx.x == 0) {
-    *done = 0u;
+    // realisation of this chunk: last r with chunk_start[r] <= blockIdx.x
+    int lo = 0, hi = n_real - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (chunk_start[mid] <= (int)blockIdx.x) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint32_t nch = (uint32_t)(chunk_start[lo + 1] - chunk_start[lo]);
+    last_r = atomicAdd(&done[1 + lo], 1u) == nch - 1 ? lo : -1;
+  }
+  __syncthreads();
+  const int r = last_r;
+  if (r >= 0 && wave == 0) {
+    __threadfence();
+    const int c0 = chunk_start[r], c1 = chunk_start[r + 1];
+    double a[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a[v] = 0.0;
+    for (int c = c0 + lane; c < c1; c += 64) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (v < S1)
+          a[v] += __hip_atomic_load(&chunk_part[(int64_t)c * S1 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int ri = 0, rr = NV;
+    halve_sum<1, 64, NV, NV>(a, ri, rr, lane);
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+      if (k < rr && lane < (1 << NB) && ri + k < S1) out[(int64_t)r * S1 + ri + k] = a[k];
+    if (lane == 0) done[1 + r] = 0u;
+  }
+  if (threadIdx.x == 0 && atomicAdd(&done[0], 1u) == (uint32_t)(nchunks - 1)) {
+    done[0] = 0u;
     if (bump) *step_ctr = *step_ctr + 1;
   }
 }
@@ -1659,6 +1693,7 @@ hipError_t launch_audit_reduce(const double* part, int32_t S1, const int2* chunk
                                double* out, uint32_t* done, uint64_t* step_ctr, int32_t bump,
                                hipStream_t s) {
   if (n_real <= 0 || nchunks <= 0) return hipSuccess;
+  if (S1 < 1 || S1 > kAuditValues) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_audit, dim3((unsigned)nchunks), dim3(kBlock), 0, s, part, S1, chunks, nchunks,
                      chunk_part, chunk_start, n_real, out, done, step_ctr, bump);
   return hipGetLastError();

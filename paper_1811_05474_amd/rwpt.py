@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "RWPT_OK", -1: "RWPT_EINVAL", -2: "RWPT_ENOMEM", -3: "RWPT_ED
 
 # Every symbol include/rwpt.h declares.
 EXPORTED = [
-    "rwpt_config_default", "rwpt_create", "rwpt_init_ensemble", "rwpt_step", "rwpt_sync",
+    "rwpt_config_default", "rwpt_create", "rwpt_init_ensemble", "rwpt_init_ensemble_device",
+    "rwpt_step", "rwpt_sync", "rwpt_stats",
     "rwpt_query_masses", "rwpt_query_positions", "rwpt_audit", "rwpt_steps_taken",
     "rwpt_count_pairs", "rwpt_neighbors", "rwpt_profile_enable", "rwpt_profile_reset",
     "rwpt_profile_read", "rwpt_profile_phase_name", "rwpt_get_tiling", "rwpt_autotune",
@@ -56,6 +57,23 @@ class rwpt_config(ctypes.Structure):
     ]
 
 
+class rwpt_stats_t(ctypes.Structure):
+    _fields_ = [
+        ("n_particles", ctypes.c_int64),
+        ("n_real", ctypes.c_int32),
+        ("tile_lanes", ctypes.c_int32),
+        ("cell_refine", ctypes.c_double * 3),
+        ("n_cells", ctypes.c_int64),
+        ("steps_taken", ctypes.c_int64),
+        ("ordered_pairs", ctypes.c_int64),
+        ("candidate_evals", ctypes.c_int64),
+        ("n_phases", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("phase_ms", ctypes.c_double * 16),
+        ("phase_launches", ctypes.c_int64 * 16),
+    ]
+
+
 class RwptError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__("%s: %s" % (STATUS_NAMES.get(status, str(status)), msg))
@@ -79,6 +97,8 @@ def load_library(path: str = LIB_PATH):
         "rwpt_config_default": (None, [pcfg]),
         "rwpt_create": (i32, [pcfg, ctypes.POINTER(vp)]),
         "rwpt_init_ensemble": (i32, [vp, i32, vp, vp, vp, vp]),
+        "rwpt_init_ensemble_device": (i32, [vp, i32, vp, vp, vp, vp]),
+        "rwpt_stats": (i32, [vp, ctypes.POINTER(rwpt_stats_t)]),
         "rwpt_step": (i32, [vp, f64, f64, i32]),
         "rwpt_sync": (i32, [vp]),
         "rwpt_query_masses": (i32, [vp, vp]),
@@ -141,6 +161,31 @@ def rwpt_init_ensemble(ctx, n_per_real, pos: np.ndarray, mass: np.ndarray, d_sca
     st = load_library().rwpt_init_ensemble(ctx, int(sizes.size), _p(sizes), _p(pos), _p(mass),
                                            None if ds is None else _p(ds))
     _check(st, ctx)
+
+
+def rwpt_init_ensemble_device(ctx, n_per_real, pos_dev_ptr: int, mass_dev_ptr: int, d_scale=None):
+    """pos_dev_ptr / mass_dev_ptr: device addresses of contiguous binary64
+    arrays in the layouts of rwpt_init_ensemble (e.g. ``tensor.data_ptr()``)."""
+    sizes = np.ascontiguousarray(np.asarray(n_per_real, dtype=np.int64).reshape(-1))
+    ds = None
+    if d_scale is not None:
+        ds = np.ascontiguousarray(np.asarray(d_scale, dtype=np.float64).reshape(-1))
+        assert ds.size == sizes.size
+    st = load_library().rwpt_init_ensemble_device(ctx, int(sizes.size), _p(sizes),
+                                                  ctypes.c_void_p(pos_dev_ptr), ctypes.c_void_p(mass_dev_ptr),
+                                                  None if ds is None else _p(ds))
+    _check(st, ctx)
+
+
+def rwpt_stats(ctx) -> dict:
+    st = rwpt_stats_t()
+    lib = load_library()
+    _check(lib.rwpt_stats(ctx, ctypes.byref(st)), ctx)
+    out = {name: getattr(st, name) for name, _ in rwpt_stats_t._fields_ if name not in ("pad", "phase_ms", "phase_launches")}
+    out["cell_refine"] = tuple(st.cell_refine)
+    out["phases"] = {lib.rwpt_profile_phase_name(i).decode(): (float(st.phase_ms[i]), int(st.phase_launches[i]))
+                     for i in range(st.n_phases)}
+    return out
 
 
 def rwpt_step(ctx, dt: float, D: float, n_steps: int = 1):
@@ -289,6 +334,9 @@ class Ensemble:
 
     def count_pairs(self, dt, D):
         return rwpt_count_pairs(self.ctx, dt, D)
+
+    def stats(self):
+        return rwpt_stats(self.ctx)
 
     def neighbors(self, dt, D):
         return rwpt_neighbors(self.ctx, dt, D, self.n)

@@ -136,3 +136,28 @@ def test_valid_init_without_gpu_reports_device_error(lib):
 
 def test_destroy_null_is_allowed(lib):
     lib.rwpt_destroy(None)
+
+
+def test_stats_struct_matches_c_layout(lib):
+    # offsets of the C struct: 4 x 8-byte header fields, 3 doubles, 4 int64,
+    # two int32, 16 doubles, 16 int64
+    assert ctypes.sizeof(rwpt.rwpt_stats_t) == 8 + 4 + 4 + 24 + 8 * 4 + 4 + 4 + 16 * 8 + 16 * 8
+    ctx = rwpt.rwpt_create(rwpt.rwpt_config_default())
+    try:
+        st = rwpt.rwpt_stats(ctx)  # before init: no device work
+        assert st["n_particles"] == 0 and st["ordered_pairs"] == -1 and st["n_cells"] == 0
+    finally:
+        rwpt.rwpt_destroy(ctx)
+
+
+def test_device_init_validates_before_copy(lib):
+    ctx = rwpt.rwpt_create(rwpt.rwpt_config_default())
+    try:
+        with pytest.raises(rwpt.RwptError) as ei:
+            rwpt.rwpt_init_ensemble_device(ctx, [-1], 0, 0)
+        assert ei.value.status == rwpt.RWPT_EINVAL
+        with pytest.raises(rwpt.RwptError) as ei:
+            rwpt.rwpt_init_ensemble_device(ctx, [4], 0, 0)
+        assert ei.value.status == rwpt.RWPT_EINVAL and "NULL" in str(ei.value)
+    finally:
+        rwpt.rwpt_destroy(ctx)

@@ -571,3 +571,50 @@ def test_private_lists_cached_and_missed_neighbours(dim, mean_nb, prec, tol, nor
     pairs, _ = ens.count_pairs(dt, D)
     assert 0.5 * mean_nb * n < pairs < 1.5 * mean_nb * n
     ens.close()
+
+
+# ---------------------------------------------- device input and state summary ----
+
+def test_init_from_device_buffers_matches_host_init():
+    import torch
+    n, seed = 5000, 31
+    x = W.positions(n, 2, seed)
+    M = W.masses(n, 2, seed)
+    xd = torch.from_numpy(x).to("cuda").contiguous()
+    Md = torch.from_numpy(M).to("cuda").contiguous()
+    torch.cuda.synchronize()
+    a = make(dim=2, rw=1.0, prec=F64, seed=seed)
+    a.init([n], x, M)
+    b = make(dim=2, rw=1.0, prec=F64, seed=seed)
+    rwpt.rwpt_init_ensemble_device(b.ctx, [n], xd.data_ptr(), Md.data_ptr())
+    b.n, b.n_real = n, 1
+    assert np.array_equal(a.audit(), b.audit())
+    a.step(0.1, 2e-4, 3)
+    b.step(0.1, 2e-4, 3)
+    assert np.array_equal(a.masses(), b.masses())
+    assert np.array_equal(a.positions(), b.positions())
+    # device input is validated like host input
+    bad = xd.clone()
+    bad[7, 1] = 2.0
+    torch.cuda.synchronize()
+    with pytest.raises(rwpt.RwptError) as ei:
+        rwpt.rwpt_init_ensemble_device(b.ctx, [n], bad.data_ptr(), Md.data_ptr())
+    assert ei.value.status == rwpt.RWPT_EINVAL and "outside" in str(ei.value)
+    a.close()
+    b.close()
+
+
+def test_stats_summarise_the_state():
+    n, D, dt = 20000, 2e-4, 0.1
+    ens = make(dim=2, rw=1.0, prec=F32, seed=3)
+    ens.init([n], f32(W.positions(n, 2, 3)), f32(W.masses(n, 2, 3)))
+    st = ens.stats()
+    assert st["n_particles"] == n and st["ordered_pairs"] == -1 and st["steps_taken"] == 0
+    rwpt.rwpt_profile_enable(ens.ctx, True)
+    ens.step(dt, D, 2)
+    st = ens.stats()
+    pairs, evals = ens.count_pairs(dt, D)
+    assert st["steps_taken"] == 2 and st["ordered_pairs"] == pairs and st["candidate_evals"] == evals
+    assert st["n_cells"] > 0 and st["tile_lanes"] == rwpt.rwpt_get_tiling(ens.ctx)[0]
+    assert st["phases"]["exchange"][1] == 2 and st["phases"]["rowsum"][1] == 2
+    ens.close()
