@@ -75,7 +75,9 @@ struct rwpt_ctx {
   std::vector<double> d_scale;
 
   DevBuf pos0, pos1, mass0, mass1, id, key, slot, tmp_src, tmp_id, tmp_key, skey, r, q;
-  DevBuf nb_meta, nb_idx, nb_w;  // neighbour cache of the one-lane-per-particle kernels
+  DevBuf nb_meta, nb_idx, nb_w, nb_src;  // neighbour cache of the one-lane-per-particle kernels
+  DevBuf src_of;                         // previous sorted slot of each sorted particle
+  int mcur = 0;                          // mass buffer holding the current masses (0: mass0, 1: mass1)
   DevBuf cell_count, cell_start, scan_part;
   DevBuf d_rp, d_st, d_tiles, d_tile_start, d_real_start;
   DevBuf audit_part, audit_out, step_ctr, counts, d_chunks, d_chunk_start, chunk_part, audit_done;
@@ -100,7 +102,8 @@ struct rwpt_ctx {
   int64_t steps = 0;
   std::vector<double> audit_init;
 
-  hipGraphExec_t gx[2] = {nullptr, nullptr};  // [0] = step with sort, [1] = without
+  // captured steps: [2 * (sort ? 0 : 1) + mcur at the start of the step]
+  hipGraphExec_t gx[4] = {nullptr, nullptr, nullptr, nullptr};
 
   bool prof = false;
   struct Ev {
@@ -175,7 +178,7 @@ static int default_lanes(int dim, int64_t n) {
 }
 
 static void invalidate_graphs(rwpt_ctx* c) {
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < 4; ++k)
     if (c->gx[k]) {
       (void)hipGraphExecDestroy(c->gx[k]);
       c->gx[k] = nullptr;
@@ -392,6 +395,7 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
     HIPCHK(c, c->nb_meta.ensure((size_t)c->cap * sizeof(uint16_t)));
     HIPCHK(c, c->nb_idx.ensure((size_t)std::max(1, c->ntiles) * kCacheWave * sizeof(uint32_t)));
     HIPCHK(c, c->nb_w.ensure((size_t)std::max(1, c->ntiles) * kCacheWave * c->tsize));
+    HIPCHK(c, c->nb_src.ensure((size_t)std::max(1, c->ntiles) * kCacheWave * sizeof(uint32_t)));
   }
   if (c->dense) {
     const int ncb = dense_ncb(c->S, c->cfg.norm);
@@ -429,13 +433,19 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   return RWPT_OK;
 }
 
+static DevBuf& mass_buf(rwpt_ctx* c, int k) { return k ? c->mass1 : c->mass0; }
+
+// Steps whose sort leaves the masses in place (the exchange reads them
+// through src_of): the one-lane-per-particle kernels of the sparse path.
+static bool masses_stay(const rwpt_ctx* c) { return !c->dense && c->log2l == kPrivateLists; }
+
 static PairArgs pair_args(rwpt_ctx* c) {
   PairArgs a;
   memset(&a, 0, sizeof(a));
   a.pos = c->pos0.p;
   a.cap = c->cap;
-  a.mass_in = c->mass1.p;
-  a.mass_out = c->mass0.p;
+  a.mass_in = mass_buf(c, c->mcur).p;
+  a.mass_out = mass_buf(c, c->mcur ^ 1).p;
   a.q_in = c->q.p;
   a.q_out = c->q.p;
   a.r_out = c->r.as<double>();
@@ -454,12 +464,17 @@ static PairArgs pair_args(rwpt_ctx* c) {
   a.nb_meta = c->nb_meta.as<uint16_t>();
   a.nb_idx = c->nb_idx.as<uint32_t>();
   a.nb_w = c->nb_w.p;
+  a.nb_src = c->nb_src.as<uint32_t>();
+  a.src_of = c->src_of.as<uint32_t>();
+  a.indirect = 0;
   return a;
 }
 
 // Sort into the cell grid: [walk] -> key -> counting sort -> canonical order.
-// Leaves positions in pos0, masses in mass1, ids in id, keys in skey.
-static rwpt_status enqueue_sort(rwpt_ctx* c, bool walk) {
+// Leaves positions in pos0, ids in id, keys in skey; the masses move to the
+// other buffer in the new order (mcur flips), or, with move_mass false, stay
+// where they are and src_of records each sorted particle's previous slot.
+static rwpt_status enqueue_sort(rwpt_ctx* c, bool walk, bool move_mass) {
   const int fp64 = c->cfg.precision == RWPT_FP64;
   const int32_t n = (int32_t)c->N;
   {
@@ -485,31 +500,35 @@ static rwpt_status enqueue_sort(rwpt_ctx* c, bool walk) {
     PhaseScope ps(c, PH_CANON);
     HIPCHK(c, launch_canon(fp64, c->dim, n, c->tmp_src.as<uint32_t>(), c->tmp_id.as<uint32_t>(),
                            c->tmp_key.as<uint32_t>(), c->cell_start.as<uint32_t>(), c->pos1.p, c->pos0.p,
-                           c->cap, c->mass0.p, c->mass1.p, c->S, c->id.as<uint32_t>(),
-                           c->skey.as<uint32_t>(), c->stream));
+                           c->cap, mass_buf(c, c->mcur).p, mass_buf(c, c->mcur ^ 1).p, c->S,
+                           c->id.as<uint32_t>(), c->skey.as<uint32_t>(),
+                           move_mass ? nullptr : c->src_of.as<uint32_t>(), c->stream));
   }
+  if (move_mass) c->mcur ^= 1;
   return RWPT_OK;
 }
 
-// One explicit step.  Masses start and end in mass0; positions in pos0.
+// One explicit step.  Positions in pos0; the masses are read from buffer
+// mcur (in the previous sorted order when the sort left them in place) and
+// the updated masses are written, in the current sorted order, to the other
+// buffer, which becomes mcur.
 static rwpt_status enqueue_step(rwpt_ctx* c, bool sort, bool walk) {
   const int fp64 = c->cfg.precision == RWPT_FP64;
+  const bool stay = sort && masses_stay(c);
   if (sort) {
-    rwpt_status st = enqueue_sort(c, walk);
+    rwpt_status st = enqueue_sort(c, walk, !stay);
     if (st != RWPT_OK) return st;
-  } else {
-    HIPCHK(c, hipMemcpyAsync(c->mass1.p, c->mass0.p, (size_t)padded_species(c->S) * c->cap * c->tsize,
-                             hipMemcpyDeviceToDevice, c->stream));
   }
   PairArgs a = pair_args(c);
+  a.indirect = stay ? 1 : 0;
   if (c->dense && c->h_rp[0].active) {
     DenseArgs da;
     memset(&da, 0, sizeof(da));
     da.pos = c->pos0.as<float>();
     da.cap = c->cap;
     da.n = (int32_t)c->N;
-    da.mass_in = c->mass1.as<float>();
-    da.mass_out = c->mass0.as<float>();
+    da.mass_in = mass_buf(c, c->mcur).as<float>();
+    da.mass_out = mass_buf(c, c->mcur ^ 1).as<float>();
     da.q = c->q.as<float>();
     da.r = c->r.as<double>();
     da.bbox = c->bbox.as<float>();
@@ -534,6 +553,7 @@ static rwpt_status enqueue_step(rwpt_ctx* c, bool sort, bool walk) {
     PhaseScope ps(c, PH_EXCHANGE);
     HIPCHK(c, launch_exchange(fp64, c->dim, c->log2l, a, c->stream));
   }
+  c->mcur ^= 1;
   {
     PhaseScope ps(c, PH_AUDIT);
     HIPCHK(c, launch_audit_reduce(c->audit_part.as<double>(), c->S + 1, c->d_chunks.as<int2>(),
@@ -544,13 +564,14 @@ static rwpt_status enqueue_step(rwpt_ctx* c, bool sort, bool walk) {
   return RWPT_OK;
 }
 
+// Flips of mcur in one step: the exchange always writes the other buffer; a
+// sort that moves the masses flips once more.
+static int step_flips(const rwpt_ctx* c, bool sort) { return (sort && !masses_stay(c)) ? 0 : 1; }
+
 static rwpt_status ensure_sorted(rwpt_ctx* c) {
   if (c->sorted_valid) return RWPT_OK;
-  rwpt_status st = enqueue_sort(c, false);
+  rwpt_status st = enqueue_sort(c, false, true);  // masses follow into the sorted order
   if (st != RWPT_OK) return st;
-  // enqueue_sort leaves masses in mass1; bring them back to mass0
-  HIPCHK(c, hipMemcpyAsync(c->mass0.p, c->mass1.p, (size_t)padded_species(c->S) * c->cap * c->tsize,
-                           hipMemcpyDeviceToDevice, c->stream));
   c->sorted_valid = true;
   return RWPT_OK;
 }
@@ -703,6 +724,8 @@ rwpt_status rwpt_init_ensemble(rwpt_ctx* c, int32_t n_real, const int64_t* n_per
   // unused species slots stay zero for the lifetime of the ensemble
   HIPCHK(c, hipMemsetAsync(c->mass0.p, 0, Sa * cap * ts, c->stream));
   HIPCHK(c, hipMemsetAsync(c->mass1.p, 0, Sa * cap * ts, c->stream));
+  c->mcur = 0;  // the loaded masses go to mass0
+  HIPCHK(c, c->src_of.ensure(cap * 4));
   HIPCHK(c, c->id.ensure(cap * 4));
   HIPCHK(c, c->key.ensure(cap * 4));
   HIPCHK(c, c->slot.ensure(cap * 4));
@@ -818,12 +841,15 @@ rwpt_status rwpt_step(rwpt_ctx* c, double dt, double D, int32_t n_steps) {
   for (int32_t it = 0; it < n_steps; ++it) {
     const bool sort = walk || !c->sorted_valid;
     if (c->cfg.use_graph && !c->prof) {
-      hipGraphExec_t& gx = c->gx[sort ? 0 : 1];
+      // a captured step bakes in the buffers of the mass parity it starts from
+      const int m0 = c->mcur;
+      hipGraphExec_t& gx = c->gx[2 * (sort ? 0 : 1) + m0];
       if (!gx) {
         hipGraph_t g = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         rwpt_status s2 = enqueue_step(c, sort, walk);
         hipError_t ec = hipStreamEndCapture(c->stream, &g);
+        c->mcur = m0;  // capture records the step; it runs at the launch below
         if (s2 != RWPT_OK) {
           if (g) (void)hipGraphDestroy(g);
           return s2;
@@ -834,6 +860,7 @@ rwpt_status rwpt_step(rwpt_ctx* c, double dt, double D, int32_t n_steps) {
         HIPCHK(c, ei);
       }
       HIPCHK(c, hipGraphLaunch(gx, c->stream));
+      c->mcur = m0 ^ step_flips(c, sort);
     } else {
       st = enqueue_step(c, sort, walk);
       if (st != RWPT_OK) return st;
@@ -881,7 +908,7 @@ rwpt_status rwpt_query_masses(rwpt_ctx* c, double* out) {
   c->err.clear();
   if (!c->initialized) return fail(c, RWPT_ESTATE, "query before rwpt_init_ensemble");
   if (!out && c->N > 0) return fail(c, RWPT_EINVAL, "out is NULL");
-  return fetch_sorted(c, c->mass0, c->S, padded_species(c->S), out, true);
+  return fetch_sorted(c, mass_buf(c, c->mcur), c->S, padded_species(c->S), out, true);
 }
 
 rwpt_status rwpt_query_positions(rwpt_ctx* c, double* out) {
@@ -1190,7 +1217,7 @@ rwpt_status rwpt_autotune(rwpt_ctx* c, double dt, double D, int32_t trial_steps)
       break;
     }
     hipError_t e = hipMemcpyAsync(sp.p, c->pos0.p, npos, hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(sm.p, c->mass0.p, nmass, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(sm.p, mass_buf(c, c->mcur).p, nmass, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(si.p, c->id.p, cap * 4, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sa.p, c->audit_out.p, naud, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sc.p, c->step_ctr.p, 8, hipMemcpyDeviceToDevice, c->stream);
@@ -1203,6 +1230,7 @@ rwpt_status rwpt_autotune(rwpt_ctx* c, double dt, double D, int32_t trial_steps)
     auto restore = [&]() -> hipError_t {
       hipError_t r = hipMemcpyAsync(c->pos0.p, sp.p, npos, hipMemcpyDeviceToDevice, c->stream);
       if (r == hipSuccess) r = hipMemcpyAsync(c->mass0.p, sm.p, nmass, hipMemcpyDeviceToDevice, c->stream);
+      c->mcur = 0;
       if (r == hipSuccess) r = hipMemcpyAsync(c->id.p, si.p, cap * 4, hipMemcpyDeviceToDevice, c->stream);
       if (r == hipSuccess) r = hipMemcpyAsync(c->audit_out.p, sa.p, naud, hipMemcpyDeviceToDevice, c->stream);
       if (r == hipSuccess) r = hipMemcpyAsync(c->step_ctr.p, sc.p, 8, hipMemcpyDeviceToDevice, c->stream);
@@ -1263,6 +1291,7 @@ rwpt_status rwpt_autotune(rwpt_ctx* c, double dt, double D, int32_t trial_steps)
     if (sp.p && sm.p && si.p && sa.p && sc.p) {
       (void)hipMemcpyAsync(c->pos0.p, sp.p, npos, hipMemcpyDeviceToDevice, c->stream);
       (void)hipMemcpyAsync(c->mass0.p, sm.p, nmass, hipMemcpyDeviceToDevice, c->stream);
+      c->mcur = 0;
       (void)hipMemcpyAsync(c->id.p, si.p, cap * 4, hipMemcpyDeviceToDevice, c->stream);
       (void)hipMemcpyAsync(c->audit_out.p, sa.p, naud, hipMemcpyDeviceToDevice, c->stream);
       (void)hipMemcpyAsync(c->step_ctr.p, sc.p, 8, hipMemcpyDeviceToDevice, c->stream);
@@ -1301,7 +1330,8 @@ void rwpt_destroy(rwpt_ctx* c) {
                       &c->cell_start, &c->scan_part, &c->d_rp, &c->d_st, &c->d_tiles,
                       &c->d_tile_start, &c->d_real_start, &c->audit_part, &c->audit_out,
                       &c->step_ctr, &c->counts, &c->d_chunks, &c->d_chunk_start, &c->chunk_part,
-                      &c->audit_done, &c->bbox, &c->bparts, &c->nb_meta, &c->nb_idx, &c->nb_w};
+                      &c->audit_done, &c->bbox, &c->bparts, &c->nb_meta, &c->nb_idx, &c->nb_w,
+                      &c->nb_src, &c->src_of};
     for (DevBuf* b : bufs) b->release();
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }

@@ -66,6 +66,11 @@ struct PairArgs {
   uint16_t* nb_meta;       // [cap]: (offset in the wave's region << 4) | count, or the miss code
   uint32_t* nb_idx;        // [ntiles][kCacheWave] sorted index j of each cached neighbour
   void* nb_w;              // [ntiles][kCacheWave] its weight w_ij (binary32 or binary64)
+  uint32_t* nb_src;        // [ntiles][kCacheWave] src_of[j] of each cached neighbour (indirect mode)
+  // indirect mode (one lane per particle after a sort): the masses are still
+  // in the previous sorted order; particle i's are at mass_in[SP * src_of[i]]
+  const uint32_t* src_of;  // [cap] previous sorted slot of each sorted particle
+  int32_t indirect;
 };
 
 }  // namespace rwpt

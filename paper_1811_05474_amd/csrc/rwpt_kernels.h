@@ -41,12 +41,14 @@ hipError_t launch_scatter(int32_t n, const uint32_t* key, const uint32_t* slot,
                           uint32_t* tmp_id, uint32_t* tmp_key, hipStream_t s);
 
 // Reorder inside every cell by particle id (canonical order), gathering
-// positions, masses, ids and keys into the sorted arrays.
+// positions, ids and keys into the sorted arrays, and the masses too when
+// src_out is NULL; otherwise the masses stay in the previous order and
+// src_out[i] receives the previous slot of sorted particle i.
 hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
                         const uint32_t* tmp_id, const uint32_t* tmp_key,
                         const uint32_t* cell_start, const void* pos_in, void* pos_out,
                         int64_t cap, const void* mass_in, void* mass_out, int32_t S,
-                        uint32_t* id_out, uint32_t* skey, hipStream_t s);
+                        uint32_t* id_out, uint32_t* skey, uint32_t* src_out, hipStream_t s);
 
 // Species slots per particle the mass arrays hold for S species: the kernels
 // are instantiated for 2, 4 or 8 species and read every slot of their

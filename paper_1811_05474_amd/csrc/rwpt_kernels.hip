@@ -348,12 +348,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int32_t n, const uint32_t* _
 // The atomic slot of the scatter depends on arrival order; ranking by the
 // (unique) particle id inside each cell makes the sorted order a function of
 // the positions alone: (cell, id).
-template <typename T, int DIM, int SMAX>
+// MOVE: gather the masses into the new order; otherwise record each sorted
+// particle's previous slot (src_out) and leave the masses where they are.
+template <typename T, int DIM, int SMAX, bool MOVE>
 __global__ __launch_bounds__(kBlock) void k_canon(
     int32_t n, const uint32_t* __restrict__ tmp_src, const uint32_t* __restrict__ tmp_id,
     const uint32_t* __restrict__ tmp_key, const uint32_t* __restrict__ cell_start,
     const T* __restrict__ pos_in, T* __restrict__ pos_out, int64_t cap, const T* __restrict__ mass_in,
-    T* __restrict__ mass_out, int32_t S, uint32_t* __restrict__ id_out, uint32_t* __restrict__ skey) {
+    T* __restrict__ mass_out, int32_t S, uint32_t* __restrict__ id_out, uint32_t* __restrict__ skey,
+    uint32_t* __restrict__ src_out) {
   const int e = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (e >= n) return;
   const uint32_t k = tmp_key[e];
@@ -361,14 +364,15 @@ __global__ __launch_bounds__(kBlock) void k_canon(
   // issue the gathers first; the in-cell ranking below overlaps them
   T x[DIM], m[SMAX];
   load_pos<T, DIM>(pos_in, src, x);
-  load_mass<T, SMAX>(mass_in, src, m);  // unused species slots are zero and stay zero
+  if constexpr (MOVE) load_mass<T, SMAX>(mass_in, src, m);  // unused species slots are zero and stay zero
   const uint32_t cs = cell_start[k], ce = cell_start[k + 1];
   const uint32_t my = tmp_id[e];
   uint32_t rank = 0;
   for (uint32_t f = cs; f < ce; ++f) rank += (tmp_id[f] < my) ? 1u : 0u;
   const uint32_t dst = cs + rank;
   store_pos<T, DIM>(pos_out, dst, x);
-  store_mass<T, SMAX>(mass_out, dst, m);
+  if constexpr (MOVE) store_mass<T, SMAX>(mass_out, dst, m);
+  else src_out[dst] = src;
   id_out[dst] = my;
   skey[dst] = k;
 }
@@ -1081,13 +1085,13 @@ __device__ __forceinline__ int cell_of(const RealParams& P, int k, double v) {
   return (int)u;
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool IND>
 __global__ __launch_bounds__(kBlock) void k_rowsum_priv(
     const T* __restrict__ pos, const int64_t cap, const uint32_t* __restrict__ skey,
     const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles, const int32_t ntiles,
     const RealParams* __restrict__ rp, const StencilRow* __restrict__ st, double* __restrict__ r_out,
     T* __restrict__ q_out, uint16_t* __restrict__ nb_meta, uint32_t* __restrict__ nb_idx,
-    T* __restrict__ nb_w) {
+    T* __restrict__ nb_w, uint32_t* __restrict__ nb_src, const uint32_t* __restrict__ src_of) {
   constexpr int RB = PrivBatch<DIM>::kRowBatch, CB = PrivBatch<DIM>::kCandBatch;
   TileLane tl;
   Tile tile;
@@ -1181,12 +1185,26 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_priv(
   q_out[ii] = (T)(1.0 / acc);
   const bool miss = cnt > (uint32_t)kCacheLane || off + keep > (uint32_t)kCacheWave;
   if (!miss) {
+    // all reads first (LDS, then the previous slots), then the stores, so the
+    // lane waits for one round trip
     const int64_t e0 = wave_tile() * kCacheWave + off;
+    uint32_t cj[kCacheLane], cs[kCacheLane];
+    T cw[kCacheLane];
+#pragma unroll
+    for (int k = 0; k < kCacheLane; ++k) {
+      cj[k] = (uint32_t)k < keep ? lj[k * 64] : 0u;
+      cw[k] = (uint32_t)k < keep ? lw[k * 64] : (T)0;
+    }
+    if constexpr (IND) {
+#pragma unroll
+      for (int k = 0; k < kCacheLane; ++k) cs[k] = (uint32_t)k < keep ? src_of[cj[k]] : 0u;
+    }
 #pragma unroll
     for (int k = 0; k < kCacheLane; ++k)
       if ((uint32_t)k < keep) {
-        nb_idx[e0 + k] = lj[k * 64];
-        nb_w[e0 + k] = lw[k * 64];
+        nb_idx[e0 + k] = cj[k];
+        nb_w[e0 + k] = cw[k];
+        if constexpr (IND) nb_src[e0 + k] = cs[k];
       }
   }
   nb_meta[ii] = miss ? (uint16_t)kCacheMiss : (uint16_t)(keep ? ((off << 4) | keep) : 0u);
@@ -1196,21 +1214,22 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_priv(
 // neighbours' indices and weights (no positions, no search); a lane marked as
 // a miss walks its stencil rows as the row-sum pass did.  r_i for the row
 // normalisation comes from the row-sum pass.
-template <typename T, int DIM, int SMAX>
+template <typename T, int DIM, int SMAX, bool IND>
 __global__ __launch_bounds__(kBlock) void k_exchange_priv(
     const T* __restrict__ pos, const int64_t cap, const T* __restrict__ min_, T* __restrict__ mout,
     const T* __restrict__ q, const double* __restrict__ r_in, const uint32_t* __restrict__ skey,
     const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles, const int32_t ntiles,
     const RealParams* __restrict__ rp, const StencilRow* __restrict__ st, const int32_t S,
     const int32_t react_a, const int32_t react_b, const int32_t norm, double* __restrict__ audit_part,
-    const uint16_t* __restrict__ nb_meta, const uint32_t* __restrict__ nb_idx, const T* __restrict__ nb_w) {
+    const uint16_t* __restrict__ nb_meta, const uint32_t* __restrict__ nb_idx, const T* __restrict__ nb_w,
+    const uint32_t* __restrict__ nb_src, const uint32_t* __restrict__ src_of) {
   TileLane tl;
   Tile tile;
   if (!tile_lane_setup<0>(tiles, ntiles, tl, tile)) return;
   const RealParams& P = rp[tile.real];
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   T Mi[SMAX];
-  load_mass<T, SMAX>(min_, ii, Mi);
+  load_mass<T, SMAX>(min_, IND ? src_of[ii] : (uint32_t)ii, Mi);
   double acc[SMAX];
 #pragma unroll
   for (int s = 0; s < SMAX; ++s) acc[s] = 0.0;
@@ -1230,7 +1249,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) accc[s] = (T)0;
       for (uint32_t k0 = 0; k0 < c; k0 += NB) {
-        uint32_t jv[NB];
+        uint32_t jv[NB], sv[NB];
         T wv[NB];
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
@@ -1238,12 +1257,14 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
           const int64_t e = e0 + (ok ? k0 + u : 0);
           jv[u] = ok ? nb_idx[e] : (uint32_t)ii;
           wv[u] = ok ? nb_w[e] : (T)0;
+          if constexpr (IND) sv[u] = ok ? nb_src[e] : src_of[ii];
+          else sv[u] = jv[u];
         }
         T qj[NB], Mj[NB][SMAX];
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
           qj[u] = q[jv[u]];
-          load_mass<T, SMAX>(min_, jv[u], Mj[u]);
+          load_mass<T, SMAX>(min_, sv[u], Mj[u]);
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
@@ -1271,7 +1292,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
           const T p = sym ? w * (qi + q[j]) : w;
           rr += w;
           T mj[SMAX];
-          load_mass<T, SMAX>(min_, j, mj);
+          load_mass<T, SMAX>(min_, IND ? src_of[j] : j, mj);
 #pragma unroll
           for (int s = 0; s < SMAX; ++s) accr[s] += p * (mj[s] - Mi[s]);
         }
@@ -1523,7 +1544,7 @@ hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
                         const uint32_t* tmp_id, const uint32_t* tmp_key,
                         const uint32_t* cell_start, const void* pos_in, void* pos_out,
                         int64_t cap, const void* mass_in, void* mass_out, int32_t S,
-                        uint32_t* id_out, uint32_t* skey, hipStream_t s) {
+                        uint32_t* id_out, uint32_t* skey, uint32_t* src_out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const dim3 g(blocks_for(n)), b(kBlock);
 #define RWPT_CN(T, D)                                                                           \
@@ -1533,9 +1554,16 @@ hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
     else RWPT_CN1(T, D, 8);                                                                     \
   } while (0)
 #define RWPT_CN1(T, D, SM)                                                                      \
-  hipLaunchKernelGGL((k_canon<T, D, SM>), g, b, 0, s, n, tmp_src, tmp_id, tmp_key, cell_start,    \
-                     (const T*)pos_in, (T*)pos_out, cap, (const T*)mass_in, (T*)mass_out, S, id_out, \
-                     skey)
+  do {                                                                                          \
+    if (src_out)                                                                                \
+      hipLaunchKernelGGL((k_canon<T, D, SM, false>), g, b, 0, s, n, tmp_src, tmp_id, tmp_key,     \
+                         cell_start, (const T*)pos_in, (T*)pos_out, cap, (const T*)mass_in,     \
+                         (T*)mass_out, S, id_out, skey, src_out);                               \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_canon<T, D, SM, true>), g, b, 0, s, n, tmp_src, tmp_id, tmp_key,      \
+                         cell_start, (const T*)pos_in, (T*)pos_out, cap, (const T*)mass_in,     \
+                         (T*)mass_out, S, id_out, skey, src_out);                               \
+  } while (0)
   if (fp64) {
     if (dim == 1) RWPT_CN(double, 1);
     else if (dim == 2) RWPT_CN(double, 2);
@@ -1587,9 +1615,13 @@ hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStr
   if (log2l == kPrivateLists) {
     return dispatch_tdl(fp64, dim, 0, [&](auto t, auto d, auto) {
       using T = decltype(t);
-      hipLaunchKernelGGL((k_rowsum_priv<T, decltype(d)::value>), g, b, 0, s, (const T*)a.pos, a.cap, a.skey,
-                         a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (T*)a.q_out, a.nb_meta,
-                         a.nb_idx, (T*)a.nb_w);
+      constexpr int D = decltype(d)::value;
+#define RWPT_RSP_ARGS                                                                                 \
+  (const T*)a.pos, a.cap, a.skey, a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (T*)a.q_out,     \
+      a.nb_meta, a.nb_idx, (T*)a.nb_w, a.nb_src, a.src_of
+      if (a.indirect) hipLaunchKernelGGL((k_rowsum_priv<T, D, true>), g, b, 0, s, RWPT_RSP_ARGS);
+      else hipLaunchKernelGGL((k_rowsum_priv<T, D, false>), g, b, 0, s, RWPT_RSP_ARGS);
+#undef RWPT_RSP_ARGS
     });
   }
   if (!fp64 && log2l == 2) {
@@ -1621,10 +1653,18 @@ hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipS
 #define RWPT_EXP_ARGS                                                                                  \
   (const T*)a.pos, a.cap, (const T*)a.mass_in, (T*)a.mass_out, (const T*)a.q_in, a.r_out, a.skey,        \
       a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.S, a.react_a, a.react_b, a.norm, a.audit_part,      \
-      a.nb_meta, a.nb_idx, (const T*)a.nb_w
-      if (a.S <= 2) hipLaunchKernelGGL((k_exchange_priv<T, D, 2>), g, b, 0, s, RWPT_EXP_ARGS);
-      else if (a.S <= 4) hipLaunchKernelGGL((k_exchange_priv<T, D, 4>), g, b, 0, s, RWPT_EXP_ARGS);
-      else hipLaunchKernelGGL((k_exchange_priv<T, D, 8>), g, b, 0, s, RWPT_EXP_ARGS);
+      a.nb_meta, a.nb_idx, (const T*)a.nb_w, a.nb_src, a.src_of
+      auto go = [&](auto sm, auto ind) {
+        hipLaunchKernelGGL((k_exchange_priv<T, D, decltype(sm)::value, decltype(ind)::value>), g, b, 0, s,
+                           RWPT_EXP_ARGS);
+      };
+      auto go_s = [&](auto ind) {
+        if (a.S <= 2) go(IC<2>{}, ind);
+        else if (a.S <= 4) go(IC<4>{}, ind);
+        else go(IC<8>{}, ind);
+      };
+      if (a.indirect) go_s(std::true_type{});
+      else go_s(std::false_type{});
 #undef RWPT_EXP_ARGS
     });
   }
