@@ -618,3 +618,21 @@ def test_stats_summarise_the_state():
     assert st["n_cells"] > 0 and st["tile_lanes"] == rwpt.rwpt_get_tiling(ens.ctx)[0]
     assert st["phases"]["exchange"][1] == 2 and st["phases"]["rowsum"][1] == 2
     ens.close()
+
+
+def test_walk2d_n1e6_mixing_limited_decay_slope():
+    # Continuum asymptote of the A + B -> 0 decay from Gaussian fluctuations:
+    # sum A ~ t^(-d/4) while the particle spacing << sqrt(2 D_eff t) << box
+    # (D_eff = D + D_rw); in 2-D at 10^6 particles that is steps ~10 - 200.
+    w = W.WORKLOADS["walk2d_n1e6"]
+    x, M, sizes, _ = W.make_inputs(w)
+    ens = make(dim=2, rw=1.0, prec=F32, seed=w.seed)
+    ens.init(sizes, x, M)
+    marks, sums, done = [20, 40, 80, 160], [], 0
+    for m in marks:
+        ens.step(w.dt, w.D, m - done)
+        done = m
+        sums.append(ens.audit()[0, 0])
+    slope = np.polyfit(np.log(marks), np.log(sums), 1)[0]
+    assert -0.6 < slope < -0.4, slope
+    ens.close()

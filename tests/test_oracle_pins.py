@@ -294,3 +294,99 @@ def test_walk_draws_depend_only_on_id_step_seed():
     b = oracle.normals(17, 5, 3)
     c = oracle.normals(17, 5, 4)
     assert np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+# ----------------------------------------------- the transfer operator T ----
+# One step with fixed positions is M' = M T^T for a matrix T that does not
+# depend on M (linearity); transferring the unit masses e_j (as N species)
+# gives T column by column.
+
+def _operator(x, D, dt, norm, kappa=3.0):
+    # rows of the result are unit-mass species: entry (j, i) = T_ij
+    n = x.shape[0]
+    eye = np.eye(n)
+    blocks = [oracle.transfer(x, eye[b:b + 64], D, dt, kappa=kappa, norm=norm, prec=64, react=None)
+              for b in range(0, n, 64)]
+    return np.concatenate(blocks, axis=0)
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_transfer_operator_symmetry_and_unit_sums(d):
+    n = 60
+    x = W.positions(n, d, 70 + d)
+    D, dt = 4e-3, 0.1
+    Ts = _operator(x, D, dt, oracle.NORM_SYM)
+    Tr = _operator(x, D, dt, oracle.NORM_ROW)
+    # SYM: P_ij = P_ji is computed identically from both ends, so T is
+    # symmetric bit for bit; its rows and columns sum to 1 (uniform masses
+    # stay put, total mass is conserved)
+    assert np.array_equal(Ts, Ts.T)
+    assert np.allclose(Ts.sum(axis=0), 1.0, rtol=0, atol=1e-15)
+    assert np.allclose(Ts.sum(axis=1), 1.0, rtol=0, atol=1e-15)
+    # ROW: rows still sum to 1, columns do not (mass is not conserved)
+    assert np.allclose(Tr.sum(axis=0), 1.0, rtol=0, atol=1e-15)
+    assert np.abs(Tr.sum(axis=1) - 1.0).max() > 1e-4
+    # the row sums r_i include the self weight
+    _, r = oracle.transfer(x, W.masses(n, 2, 1), D, dt, kappa=3.0, prec=64, react=None, return_r=True)
+    assert np.all(r >= 1.0)
+
+
+def test_mixing_limited_decay_matches_its_exact_expectation():
+    # A - B = delta evolves by T with or without the reaction, and after the
+    # reaction A = max(delta, 0).  With Gaussian mass fluctuations delta(0) has
+    # independent entries of variance v0 = 2 (0.1 / N)^2 and mean 0, so
+    # E[sum_i A_i(n)] = sqrt(v0 / 2 pi) sum_i || row i of T^n ||_2  exactly,
+    # for fixed positions.  The oracle with the reaction is checked against
+    # this over independent mass draws (statistically, within 4 standard
+    # errors), which pins transfer and reaction together.
+    n, D, dt, steps, draws = 120, 3.5e-4, 0.1, 8, 400
+    x = W.positions(n, 1, 77)
+    T = _operator(x, D, dt, oracle.NORM_SYM).T   # M' = T M for one species row
+    v0 = 2.0 * (0.1 / n) ** 2
+    expect, Tn = [], np.eye(n)
+    for _ in range(steps):
+        Tn = T @ Tn
+        expect.append(math.sqrt(v0 / (2.0 * math.pi)) * np.linalg.norm(Tn, axis=1).sum())
+    sums = np.zeros((draws, steps))
+    for k in range(draws):
+        M = W.masses(n, 2, 1000 + k)
+        for s in range(steps):
+            M = oracle.transfer(x, M, D, dt, kappa=3.0, prec=64, react=(0, 1))
+            sums[k, s] = M[0].sum()
+    mean = sums.mean(axis=0)
+    se = sums.std(axis=0, ddof=1) / math.sqrt(draws)
+    assert np.all(np.abs(mean - np.array(expect)) < 4.0 * se)
+    # and the decay is monotone
+    assert np.all(np.diff(expect) < 0)
+
+
+def test_well_mixed_decay_reaches_the_global_excess():
+    # every weight 1: delta relaxes to its mean by 2^-n, so sum A -> max(sum delta, 0)
+    n = 200
+    x = W.positions(n, 2, 5)
+    for seed in (3, 4):
+        M = W.masses(n, 2, seed)
+        excess = max((M[0] - M[1]).sum(), 0.0)
+        for _ in range(45):
+            M = oracle.transfer(x, M, 1e12, 0.1, kappa=math.inf, react=(0, 1))
+        assert abs(M[0].sum() - excess) < 1e-13 * np.abs(M).sum()
+        assert abs(M[1].sum() - max(-(M[0] - M[1]).sum(), 0.0)) < 1e-13 * np.abs(M).sum()
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_cutoff_gap_is_bounded_by_the_neglected_kernel_mass(d):
+    # w = exp(-s^2 / sigma^2) is a Gaussian of variance sigma^2 / 2 per axis;
+    # the fraction of its mass beyond s = 3 sigma is erfc(3) in 1-D, e^-9 in
+    # 2-D and erfc(3) + (6 / sqrt(pi)) e^-9 in 3-D.  Dropping it changes each
+    # transfer by at most that fraction of the mass differences.
+    from scipy.special import erfc
+    n = {1: 1000, 2: 1500, 3: 1500}[d]
+    x = f32(W.positions(n, d, 50 + d))
+    M = W.masses(n, 2, 50 + d)
+    rc = {1: 0.03, 2: 0.08, 3: 0.2}[d]
+    D = (rc / 3.0) ** 2 / (8 * 0.1)
+    dense = oracle.transfer(x, M, D, 0.1, kappa=math.inf, react=None)
+    sparse = oracle.transfer(x, M, D, 0.1, kappa=3.0, prec=64, react=None)
+    gap = np.abs(sparse - dense).max() / np.abs(M).max()
+    tail = {1: erfc(3.0), 2: math.exp(-9.0), 3: erfc(3.0) + 6.0 / math.sqrt(math.pi) * math.exp(-9.0)}[d]
+    assert tail / 1000 < gap < tail
