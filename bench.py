@@ -271,7 +271,7 @@ def main():
         "peak": PEAK_FP32_VECTOR_TFLOPS,
         "unit": "TFLOP/s",
         "frac": achieved_tflops / PEAK_FP32_VECTOR_TFLOPS,
-        "traffic": measured_traffic("k_exchange_" + w.name),
+        "traffic": measured_traffic(("k_dense_exchange_" if dense else "k_exchange_") + w.name),
         "us_per_launch": ex["us_avg"],
         "flops_per_launch": flops_per_launch,
         "algorithmic_bytes_per_launch": alg_bytes,

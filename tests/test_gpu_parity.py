@@ -636,3 +636,24 @@ def test_walk2d_n1e6_mixing_limited_decay_slope():
     slope = np.polyfit(np.log(marks), np.log(sums), 1)[0]
     assert -0.6 < slope < -0.4, slope
     ens.close()
+
+
+def test_dense_full_matrix_at_its_maximum_size():
+    # one realisation of 2^17 particles, the largest the matrix-core path
+    # takes; sampled rows against the oracle's full matrix (every pair)
+    n, D, dt = 1 << 17, 1e-4, 0.1
+    x = f32(W.positions(n, 1, 17))
+    M = f32(W.masses(n, 2, 17))
+    ens = rwpt.Ensemble(dim=1, n_species=2, kappa=None, rw_ratio=0.0, precision=F32,
+                        path=rwpt.RWPT_PATH_DENSE, seed=17)
+    ens.init([n], x, M)
+    ens.step(dt, D, 1)
+    got = ens.masses()
+    rows = np.random.default_rng(17).choice(n, 64, replace=False)
+    # the oracle at kappa = 7 equals its full matrix to e^-49 of the kernel
+    # (far below any tolerance here) and runs on its cell grid
+    ref = oracle.transfer(x, M, D, dt, kappa=7.0, prec=32, rows=rows)
+    assert normerr(got[:, rows], ref) < 1e-5
+    a = ens.audit()[0]
+    assert abs(a[2] - oracle.audit(M)[2]) < 1e-6 * (a[0] + a[1])
+    ens.close()
