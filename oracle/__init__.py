@@ -65,6 +65,8 @@ def _load():
         lib.orc_normals.restype = None
         lib.orc_walk.argtypes = [i64, i32, vp, vp, u64, u64, f64, f64, vp, vp]
         lib.orc_walk.restype = i32
+        lib.orc_walk_adv.argtypes = [i64, i32, vp, vp, u64, u64, f64, f64, vp, vp, vp, f64, f64]
+        lib.orc_walk_adv.restype = i32
         lib.orc_neighbors.argtypes = [i64, i32, vp, f64, f64, f64, i32, vp, vp, i64]
         lib.orc_neighbors.restype = i64
         lib.orc_transfer_rows.argtypes = [i64, i32, i32, vp, vp, vp, f64, f64, f64, i32, i32, i32,
@@ -107,15 +109,28 @@ def normals(pid: int, seed: int, step: int) -> np.ndarray:
 
 
 def walk(x: np.ndarray, ids: np.ndarray, seed: int, step: int, D_rw: float, dt: float,
-         lo, hi) -> np.ndarray:
-    """Random-walk move of Eq. (1)/(2) at zero velocity with reflecting walls (Sec. 3).
+         lo, hi, velocity=None, alpha_l: float = 0.0, alpha_t: float = 0.0) -> np.ndarray:
+    """Random-walk move of Eq. (1)/(2) with reflecting walls (Sec. 3).
 
-    ``x`` is (n, d) float64; returns a new array."""
+    Without ``velocity`` the move is pure diffusion with D_rw; with a constant
+    velocity v it adds the drift v dt and the hydrodynamic dispersion of
+    Eq. (1) with dispersivities alpha_l >= alpha_t >= 0.  ``x`` is (n, d)
+    float64; returns a new array."""
     x = np.ascontiguousarray(np.array(x, dtype=np.float64, copy=True))
     n, d = x.shape
     ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
     lo = np.ascontiguousarray(np.asarray(lo, dtype=np.float64).reshape(-1)[:d])
     hi = np.ascontiguousarray(np.asarray(hi, dtype=np.float64).reshape(-1)[:d])
+    if velocity is not None:
+        vel = np.zeros(3, dtype=np.float64)
+        v = np.asarray(velocity, dtype=np.float64).reshape(-1)[:d]
+        vel[:v.size] = v
+        rc = _load().orc_walk_adv(n, d, _ptr(x), _ptr(ids), ctypes.c_uint64(seed), ctypes.c_uint64(step),
+                                  float(D_rw), float(dt), _ptr(lo), _ptr(hi), _ptr(vel), float(alpha_l),
+                                  float(alpha_t))
+        if rc != 0:
+            raise ValueError("orc_walk_adv failed (%d)" % rc)
+        return x
     rc = _load().orc_walk(n, d, _ptr(x), _ptr(ids), ctypes.c_uint64(seed), ctypes.c_uint64(step),
                           float(D_rw), float(dt), _ptr(lo), _ptr(hi))
     if rc != 0:

@@ -17,6 +17,11 @@
  *     velocity (the test problem of Sec. 3 is pure diffusion), i.e.
  *     x <- x + sqrt(2 D_rw dt) dW per dimension, followed by reflection at
  *     zero-flux walls (Sec. 3).
+ *   - orc_walk_adv: the same move with a constant velocity v and the
+ *     hydrodynamic dispersion of Eq. (1): x <- x + v dt + B dW with
+ *     B B^T = 2 dt [(D_rw + aT |v|) I + (aL - aT) v v^T / |v|], then
+ *     reflection.  (Eq. (1) prints only the (aL - aT) term in the walk; with
+ *     aT = 0, and in 1-D where Eq. (2) follows, the two agree.)
  *   - orc_neighbors: the set of particle pairs whose separation lies within
  *     the cutoff s_max = kappa*sigma (Sec. 2.1 fixed-radius search, Sec. 2.2
  *     ghost pad Delta zeta = kappa sigma with sigma = sqrt(8 D dt)).
@@ -143,6 +148,38 @@ int orc_walk(int64_t n, int d, double *x, const uint32_t *id, uint64_t seed, uin
     for (int k = 0; k < d; ++k) {
       double v = x[i * d + k] + amp * z[k];
       x[i * d + k] = reflect(v, lo[k], hi[k]);
+    }
+  }
+  return ORC_OK;
+}
+
+/* Constant velocity and dispersivities.  The covariance coefficient of the
+ * displacement is c_L = D_rw + aL |v| along u = v / |v| and c_T = D_rw + aT |v|
+ * across it, so one square root of 2 dt times the tensor applied to dW is
+ *   sqrt(2 dt c_T) dW + (sqrt(2 dt c_L) - sqrt(2 dt c_T)) (u . dW) u.
+ * With v = 0 the move is that of orc_walk, bit for bit. */
+int orc_walk_adv(int64_t n, int d, double *x, const uint32_t *id, uint64_t seed, uint64_t step,
+                 double D_rw, double dt, const double *lo, const double *hi, const double *vel,
+                 double alpha_l, double alpha_t) {
+  if (n < 0 || d < 1 || d > 3 || D_rw < 0 || dt <= 0 || alpha_t < 0 || alpha_l < alpha_t) return ORC_EINVAL;
+  double speed2 = 0.0;
+  for (int k = 0; k < d; ++k) speed2 += vel[k] * vel[k];
+  const double speed = sqrt(speed2);
+  double u[3] = {0.0, 0.0, 0.0};
+  if (speed > 0.0)
+    for (int k = 0; k < d; ++k) u[k] = vel[k] / speed;
+  const double amp_t = sqrt(2.0 * dt * (D_rw + alpha_t * speed));
+  const double amp_l = sqrt(2.0 * dt * (D_rw + alpha_l * speed));
+  const double extra = amp_l - amp_t;
+  if (speed == 0.0 && amp_t == 0.0) return ORC_OK;
+  for (int64_t i = 0; i < n; ++i) {
+    double z[3];
+    orc_normals(id[i], seed, step, z);
+    double uz = 0.0;
+    for (int k = 0; k < d; ++k) uz += u[k] * z[k];
+    for (int k = 0; k < d; ++k) {
+      const double move = vel[k] * dt + amp_t * z[k] + extra * uz * u[k];
+      x[i * d + k] = reflect(x[i * d + k] + move, lo[k], hi[k]);
     }
   }
   return ORC_OK;

@@ -61,15 +61,15 @@ WORKLOADS = {
 }
 
 
-def interface(n: int, dim: int, L, seed: int):
+def interface(n: int, dim: int, L, seed: int, x0: float | None = None):
     """Segregated initial condition of the paper's test problem (Sec. 3, 5.1):
-    uniform positions in [0, L]^dim; C1 = 1 for x > L/2 (0 below), C2 the
-    complement; masses are concentration times the particle volume
-    ds = |box| / n.  Returns positions (n, dim) and masses (2, n)."""
+    uniform positions in [0, L]^dim; C1 = 1 for x > x0 (0 below; x0 = L/2 by
+    default), C2 the complement; masses are concentration times the particle
+    volume ds = |box| / n.  Returns positions (n, dim) and masses (2, n)."""
     L = np.broadcast_to(np.asarray(L, dtype=np.float64), (dim,))
     x = positions(n, dim, seed, (0.0,) * dim, tuple(L))
     ds = float(np.prod(L)) / n
-    right = x[:, 0] > 0.5 * L[0]
+    right = x[:, 0] > (0.5 * L[0] if x0 is None else float(x0))
     M = np.stack([right * ds, (~right) * ds]).astype(np.float64)
     return x, M
 
