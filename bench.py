@@ -83,7 +83,8 @@ def ensemble_for(rwpt, w, precision, tile_lanes, kappa=None):
     kappa = w.kappa if kappa is None else kappa
     return rwpt.Ensemble(dim=w.dim, n_species=w.n_species, react=w.react, kappa=kappa,
                          rw_ratio=w.rw_ratio, precision=precision, seed=w.seed, tile_lanes=tile_lanes,
-                         box_lo=w.box_lo, box_hi=w.box_hi)
+                         box_lo=w.box_lo, box_hi=w.box_hi, velocity=w.velocity, alpha_l=w.alpha_l,
+                         alpha_t=w.alpha_t)
 
 
 def init_ensemble(ens, W, w):
@@ -156,9 +157,11 @@ def cpu_baseline(W, w, unordered_pairs_per_step, budget_s=15.0):
             if e == b:
                 continue
             xr = x[b:e]
-            if w.rw_ratio > 0:
+            if w.rw_ratio > 0 or any(w.velocity):
                 ids = np.arange(b, e, dtype=np.uint32)
-                xr = oracle.walk(xr, ids, w.seed, 0, w.rw_ratio * Ds[r], w.dt, w.box_lo, w.box_hi)
+                xr = oracle.walk(xr, ids, w.seed, 0, w.rw_ratio * Ds[r], w.dt, w.box_lo, w.box_hi,
+                                 velocity=w.velocity if any(w.velocity) else None,
+                                 alpha_l=w.alpha_l, alpha_t=w.alpha_t)
             oracle.transfer(xr, M[:, b:e], Ds[r], w.dt, kappa=w.kappa, prec=32, react=w.react)
             done += e - b
             if time.perf_counter() - t0 > budget_s:

@@ -5,10 +5,11 @@
  *
  * One call of rwpt_step advances every realisation of an ensemble by n steps.
  * A step is, in this order (Sec. 1.1 and Sec. 7 of the paper):
- *   1. the random-walk move of Eq. (1)/(2) at zero velocity,
- *      x <- x + sqrt(2 D_rw dt) dW, with reflection at the zero-flux box walls
- *      (Sec. 3); D_rw = rw_ratio * D (the "mixed" diffusion split of Sec. 2.2
- *      and Sec. 3, where each operation applies half of the total);
+ *   1. the random-walk move of Eq. (1)/(2), x <- x + sqrt(2 D_rw dt) dW (plus,
+ *      with a velocity, the drift v dt and the hydrodynamic dispersion), with
+ *      reflection at the zero-flux box walls (Sec. 3); D_rw = rw_ratio * D (the
+ *      "mixed" diffusion split of Sec. 2.2 and Sec. 3, where each operation
+ *      applies half of the total);
  *   2. the neighbour search: every pair with separation within the cutoff
  *      s_max = kappa * sigma, sigma = sqrt(8 D dt) (Sec. 2.1, Sec. 2.2);
  *   3. the co-location weights w_ij = exp(-s_ij^2 / (8 D dt)) of Eq. (3), their
@@ -94,13 +95,21 @@ typedef struct rwpt_config {
   int32_t use_graph;      /* 1 = replay each rwpt_step as one captured HIP graph */
   uint64_t seed;          /* key of the counter-based random walk */
   void *stream;           /* hipStream_t to queue work on; NULL = a stream the context owns */
+  /* Advection and hydrodynamic dispersion of the walk (Eq. 1, Eq. 2): a
+   * constant velocity v (entries beyond dim ignored) adds v dt per step, and
+   * dispersivities alpha_l >= alpha_t >= 0 add the dispersion tensor
+   * alpha_t |v| I + (alpha_l - alpha_t) v v^T / |v| to the isotropic walk
+   * share D_rw.  Zero velocity (default) gives the pure-diffusion walk. */
+  double velocity[3];
+  double alpha_l;
+  double alpha_t;
 } rwpt_config;
 
 typedef struct rwpt_ctx rwpt_ctx;
 
 /* Fill *cfg with defaults: dim 2, S 2, reaction (0, 1), unit box, kappa 3,
  * rw_ratio 1, FP32, SYM, AUTO path, automatic tiling, device 0, graphs on,
- * seed 0, NULL stream. */
+ * seed 0, NULL stream, zero velocity and dispersivities. */
 void rwpt_config_default(rwpt_config *cfg);
 
 /* Validate *cfg and create a context.  No device memory is touched until

@@ -294,7 +294,20 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
     P.p_end = c->real_start[r + 1];
     const int64_t nr = P.p_end - P.p_begin;
     const double Dr = D * c->d_scale[r];
-    P.amp = cfg.rw_ratio > 0.0 ? std::sqrt(2.0 * (cfg.rw_ratio * Dr) * dt) : 0.0;
+    {
+      // walk: isotropic share D_rw, plus drift and dispersion with a velocity
+      double speed2 = 0.0;
+      for (int k = 0; k < dim; ++k) speed2 += cfg.velocity[k] * cfg.velocity[k];
+      const double speed = std::sqrt(speed2);
+      const double Drw = cfg.rw_ratio * Dr;
+      P.amp = std::sqrt(2.0 * dt * (Drw + cfg.alpha_t * speed));
+      P.amp_x = std::sqrt(2.0 * dt * (Drw + cfg.alpha_l * speed)) - P.amp;
+      for (int k = 0; k < 3; ++k) {
+        P.drift[k] = k < dim ? cfg.velocity[k] * dt : 0.0;
+        P.udir[k] = (k < dim && speed > 0.0) ? cfg.velocity[k] / speed : 0.0;
+      }
+      P.moves = (P.amp > 0.0 || speed > 0.0) ? 1 : 0;
+    }
     P.active = Dr > 0.0 ? 1 : 0;
     int64_t nc[3] = {1, 1, 1};
     double rcg = 0.0;
@@ -607,6 +620,9 @@ void rwpt_config_default(rwpt_config* cfg) {
   cfg->use_graph = 1;
   cfg->seed = 0;
   cfg->stream = nullptr;
+  for (int k = 0; k < 3; ++k) cfg->velocity[k] = 0.0;
+  cfg->alpha_l = 0.0;
+  cfg->alpha_t = 0.0;
 }
 
 rwpt_status rwpt_create(const rwpt_config* cfg, rwpt_ctx** out) {
@@ -629,6 +645,10 @@ rwpt_status rwpt_create(const rwpt_config* cfg, rwpt_ctx** out) {
   if (!(c.kappa > 0.0)) return fail(nullptr, RWPT_EINVAL, "kappa must be > 0 (or INFINITY)");
   if (!std::isfinite(c.rw_ratio) || c.rw_ratio < 0.0)
     return fail(nullptr, RWPT_EINVAL, "rw_ratio must be finite and >= 0");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(c.velocity[k])) return fail(nullptr, RWPT_EINVAL, "velocity[%d] is not finite", k);
+  if (!std::isfinite(c.alpha_l) || !std::isfinite(c.alpha_t) || c.alpha_t < 0.0 || c.alpha_l < c.alpha_t)
+    return fail(nullptr, RWPT_EINVAL, "dispersivities must satisfy alpha_l >= alpha_t >= 0");
   if (c.precision != RWPT_FP32 && c.precision != RWPT_FP64)
     return fail(nullptr, RWPT_EINVAL, "precision must be RWPT_FP32 or RWPT_FP64");
   if (c.norm != RWPT_NORM_SYM && c.norm != RWPT_NORM_ROW)
@@ -839,7 +859,9 @@ rwpt_status rwpt_step(rwpt_ctx* c, double dt, double D, int32_t n_steps) {
   HIPCHK(c, hipSetDevice(c->cfg.device));
   rwpt_status st = build_grid(c, dt, D);
   if (st != RWPT_OK) return st;
-  const bool walk = c->cfg.rw_ratio > 0.0 && D > 0.0;
+  bool advect = false;
+  for (int k = 0; k < c->dim; ++k) advect = advect || c->cfg.velocity[k] != 0.0;
+  const bool walk = (c->cfg.rw_ratio > 0.0 && D > 0.0) || advect;
   for (int32_t it = 0; it < n_steps; ++it) {
     const bool sort = walk || !c->sorted_valid;
     if (c->cfg.use_graph && !c->prof) {

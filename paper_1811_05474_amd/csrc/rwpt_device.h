@@ -22,8 +22,13 @@ struct RealParams {
   double escale_d;     // -1 / sigma^2, sigma^2 = 8 D_r dt
   float rc2_f;         // rc2_d rounded once to binary32
   float escale_f;      // -log2(e) / sigma^2 rounded to binary32 (for exp2)
-  double amp;          // random-walk amplitude sqrt(2 D_rw dt)
+  double amp;          // isotropic walk amplitude sqrt(2 dt (D_rw + alpha_t |v|))
   double rc_geo;       // geometric cutoff sqrt(rc2_d) (1 + 1e-5): covers the rounding of s^2
+  double drift[3];     // v dt
+  double udir[3];      // v / |v| (zero without a velocity)
+  double amp_x;        // sqrt(2 dt (D_rw + alpha_l |v|)) - amp: extra amplitude along udir
+  int32_t moves;       // 1 if the walk moves particles of this realisation
+  int32_t pad_;
 };
 
 // Offset (dy, dz) of a neighbour row of cells and how many cells (rx) to

@@ -177,27 +177,39 @@ __global__ __launch_bounds__(kBlock) void k_walk_key(
     if (real_start[mid] <= p) lo = mid;
     else hi = mid - 1;
   }
-  const RealParams& P = rp[lo];
   T x[DIM];
   load_pos<T, DIM>(pos_in, p, x);
-  if (do_walk && P.amp > 0.0) {
-    T z[3];
-    walk_normals<T, DIM>(id[p], seed, *step_ctr, z);
-    const T amp = (T)P.amp;
+  auto walk_and_key = [&](const RealParams& P) -> uint32_t {
+    if (do_walk && P.moves) {
+      // drift v dt, isotropic amplitude, extra amplitude along v (Eq. 1)
+      T z[3];
+      walk_normals<T, DIM>(id[p], seed, *step_ctr, z);
+      const T amp = (T)P.amp, ampx = (T)P.amp_x;
+      T uz = (T)0;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) x[k] = reflect<T>(x[k] + amp * z[k], (T)P.lo[k], (T)P.hi[k]);
-  }
+      for (int k = 0; k < DIM; ++k) uz += (T)P.udir[k] * z[k];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        const T move = (T)P.drift[k] + amp * z[k] + ampx * uz * (T)P.udir[k];
+        x[k] = reflect<T>(x[k] + move, (T)P.lo[k], (T)P.hi[k]);
+      }
+    }
+    int64_t c = 0;
+#pragma unroll
+    for (int k = DIM - 1; k >= 0; --k) {
+      const double u = ((double)x[k] - P.lo[k]) * P.inv_h[k];
+      int ck = (int)floor(u);
+      ck = ck < 0 ? 0 : ck;
+      ck = ck > P.nc[k] - 1 ? P.nc[k] - 1 : ck;
+      c = c * P.nc[k] + ck;
+    }
+    return (uint32_t)(P.cell_off + c);
+  };
+  // realisations are contiguous, so a wave almost always lies in one: then
+  // its parameters are read once through the scalar cache
+  const int lo_u = __builtin_amdgcn_readfirstlane(lo);
+  const uint32_t key = __ballot(lo != lo_u) == 0 ? walk_and_key(rp[lo_u]) : walk_and_key(rp[lo]);
   store_pos<T, DIM>(pos_out, p, x);
-  int64_t c = 0;
-#pragma unroll
-  for (int k = DIM - 1; k >= 0; --k) {
-    const double u = ((double)x[k] - P.lo[k]) * P.inv_h[k];
-    int ck = (int)floor(u);
-    ck = ck < 0 ? 0 : ck;
-    ck = ck > P.nc[k] - 1 ? P.nc[k] - 1 : ck;
-    c = c * P.nc[k] + ck;
-  }
-  const uint32_t key = (uint32_t)(P.cell_off + c);
   key_out[p] = key;
   // The input is in cell order from the previous step, so equal new keys
   // mostly sit in runs of consecutive lanes: one atomic per run, the run's

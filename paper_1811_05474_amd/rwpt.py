@@ -54,6 +54,9 @@ class rwpt_config(ctypes.Structure):
         ("use_graph", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("stream", ctypes.c_void_p),
+        ("velocity", ctypes.c_double * 3),
+        ("alpha_l", ctypes.c_double),
+        ("alpha_t", ctypes.c_double),
     ]
 
 
@@ -283,7 +286,8 @@ class Ensemble:
 
     def __init__(self, dim=2, n_species=2, react=(0, 1), box_lo=(0.0, 0.0, 0.0), box_hi=(1.0, 1.0, 1.0),
                  kappa=3.0, rw_ratio=1.0, precision=RWPT_FP32, norm=RWPT_NORM_SYM, path=RWPT_PATH_AUTO,
-                 tile_lanes=0, cell_refine=(0.0, 0.0, 0.0), device=0, use_graph=1, seed=0, stream=None):
+                 tile_lanes=0, cell_refine=(0.0, 0.0, 0.0), device=0, use_graph=1, seed=0, stream=None,
+                 velocity=(0.0, 0.0, 0.0), alpha_l=0.0, alpha_t=0.0):
         cfg = rwpt_config_default()
         cfg.dim = dim
         cfg.n_species = n_species
@@ -302,6 +306,10 @@ class Ensemble:
         cfg.use_graph = use_graph
         cfg.seed = seed
         cfg.stream = stream
+        for k in range(3):
+            cfg.velocity[k] = velocity[k] if k < len(velocity) else 0.0
+        cfg.alpha_l = float(alpha_l)
+        cfg.alpha_t = float(alpha_t)
         self.cfg = cfg
         self.dim, self.S = dim, n_species
         self.n, self.n_real = 0, 0

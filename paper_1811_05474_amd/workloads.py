@@ -37,6 +37,10 @@ class Workload:
     n_real: int = 1
     D_choices: tuple = field(default_factory=tuple)
     init: str = "uniform"  # "uniform" masses, or the segregated "interface" of Sec. 3
+    x0: float | None = None  # interface position (default: the middle of the box)
+    velocity: tuple = (0.0, 0.0, 0.0)  # constant velocity of the walk (Eq. 1)
+    alpha_l: float = 0.0   # longitudinal dispersivity
+    alpha_t: float = 0.0   # transverse dispersivity
 
 
 WORKLOADS = {
@@ -58,6 +62,11 @@ WORKLOADS = {
     # species are the conservative components C1, C2 (no reaction term)
     "interface1d_l50": Workload("interface1d_l50", 1, 2000, 2, 0.5, 0.1, 100, 3.0, 1.0, 6000,
                                 react=None, box_hi=(50.0, 1.0, 1.0), n_real=75, init="interface"),
+    # the same interface at x0 = 10 advected with v = 1 and longitudinal
+    # dispersivity 1 (Eq. 2 plus the transfer): the front reaches x = 20 at t = 10
+    "advect1d_l50": Workload("advect1d_l50", 1, 2000, 2, 0.5, 0.1, 100, 3.0, 1.0, 8000,
+                             react=None, box_hi=(50.0, 1.0, 1.0), n_real=75, init="interface", x0=10.0,
+                             velocity=(1.0, 0.0, 0.0), alpha_l=1.0),
 }
 
 
@@ -105,7 +114,7 @@ def make_inputs(w: Workload, n: int | None = None):
     drawn with seed w.seed + r."""
     if w.init == "interface":
         n = w.n if n is None else int(n)
-        parts = [interface(n, w.dim, w.box_hi[:w.dim], w.seed + r) for r in range(w.n_real)]
+        parts = [interface(n, w.dim, w.box_hi[:w.dim], w.seed + r, x0=w.x0) for r in range(w.n_real)]
         return (np.concatenate([p[0] for p in parts], 0), np.concatenate([p[1] for p in parts], 1),
                 np.full(w.n_real, n, dtype=np.int64), np.full(w.n_real, w.D))
     if w.n_real == 1:

@@ -49,6 +49,7 @@ def test_config_struct_matches_c_layout(lib):
     ("dim", 0), ("dim", 4), ("n_species", 0), ("n_species", 9), ("react_a", 5), ("kappa", 0.0),
     ("kappa", -1.0), ("kappa", float("nan")), ("rw_ratio", -1.0), ("precision", 2), ("norm", 3),
     ("path", 7), ("tile_lanes", 3), ("tile_lanes", 32), ("tile_lanes", -2), ("device", -1), ("use_graph", 2),
+    ("alpha_t", -0.1), ("alpha_l", float("nan")),
 ])
 def test_create_rejects_bad_config(lib, field, value):
     cfg = rwpt.rwpt_config_default()
@@ -57,6 +58,20 @@ def test_create_rejects_bad_config(lib, field, value):
         rwpt.rwpt_create(cfg)
     assert ei.value.status == rwpt.RWPT_EINVAL
     assert rwpt.rwpt_last_error(None)
+
+
+def test_advection_defaults_and_validation(lib):
+    cfg = rwpt.rwpt_config_default()
+    assert list(cfg.velocity) == [0.0, 0.0, 0.0] and cfg.alpha_l == 0.0 and cfg.alpha_t == 0.0
+    cfg.velocity[1] = float("inf")
+    with pytest.raises(rwpt.RwptError):
+        rwpt.rwpt_create(cfg)
+    cfg = rwpt.rwpt_config_default()
+    cfg.alpha_l, cfg.alpha_t = 0.1, 0.2   # alpha_l < alpha_t
+    with pytest.raises(rwpt.RwptError):
+        rwpt.rwpt_create(cfg)
+    cfg.alpha_l = 0.3
+    rwpt.rwpt_destroy(rwpt.rwpt_create(cfg))
 
 
 def test_create_rejects_bad_box_and_reaction(lib):

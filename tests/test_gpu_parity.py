@@ -657,3 +657,56 @@ def test_dense_full_matrix_at_its_maximum_size():
     a = ens.audit()[0]
     assert abs(a[2] - oracle.audit(M)[2]) < 1e-6 * (a[0] + a[1])
     ens.close()
+
+
+# ------------------------------------------- advection and dispersion (Eq. 1) ----
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("prec,tol", [(F32, 1e-5), (F64, 1e-12)])
+def test_advective_walk_replayed(dim, prec, tol):
+    n, D, dt, seed = 20000, 1e-4, 0.1, 123
+    vel = (0.02, -0.015, 0.01)[:dim]
+    aL, aT = 0.01, 0.002
+    x = W.positions(n, dim, seed)
+    M = W.masses(n, 2, seed)
+    if prec == F32:
+        x, M = f32(x), f32(M)
+    lo, hi = (0.0,) * dim, (1.0,) * dim
+    ens = rwpt.Ensemble(dim=dim, n_species=2, rw_ratio=1.0, precision=prec, seed=seed, velocity=vel,
+                        alpha_l=aL, alpha_t=aT)
+    ens.init([n], x, M)
+    xcur, mcur = x, M
+    for step in range(3):
+        ens.step(dt, D, 1)
+        pos, got = ens.positions(), ens.masses()
+        walked = oracle.walk(xcur, np.arange(n), seed, step, D, dt, lo, hi, velocity=vel, alpha_l=aL, alpha_t=aT)
+        assert np.abs(pos - walked).max() < (2e-6 if prec == F32 else 1e-12)
+        ref = oracle.transfer(pos, mcur, D, dt, kappa=3.0, prec=32 if prec == F32 else 64)
+        assert normerr(got, ref) < tol, (step, normerr(got, ref))
+        xcur, mcur = pos, got
+    ens.close()
+
+
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_advected_interface_follows_the_shifted_erfc(prec):
+    # 1-D interface at x0 = 10 on [0, 50] advected with v = 1 for t = 10, transfer
+    # D_m = 0.5, walk share 0.5, longitudinal dispersivity 1: C1 follows
+    # erfc((x0 + v t - x) / sqrt(4 (D_m + D_rw + alpha_L v) t)) / 2 near the front
+    from scipy.special import erfc
+    L, n, R, x0, v, aL = 50.0, 4000, 3, 10.0, 1.0, 1.0
+    parts = [W.interface(n, 1, L, 8000 + r, x0=x0) for r in range(R)]
+    x = np.concatenate([p[0] for p in parts])
+    M = np.concatenate([p[1] for p in parts], 1)
+    ens = rwpt.Ensemble(dim=1, n_species=2, react=None, rw_ratio=1.0, precision=prec, seed=8000,
+                        box_hi=(L, 1, 1), velocity=(v, 0, 0), alpha_l=aL)
+    ens.init([n] * R, x, M)
+    ens.step(0.1, 0.5, 100)
+    pos, got = ens.positions()[:, 0], ens.masses()
+    front = x0 + v * 10.0
+    sel = np.abs(pos - front) < 8.0
+    exact = 0.5 * erfc((front - pos[sel]) / math.sqrt(4 * (0.5 + 0.5 + aL * v) * 10.0))
+    rmse = math.sqrt(np.mean((got[0][sel] / (L / n) - exact) ** 2))
+    assert rmse < 0.045, rmse
+    # the components stay complementary
+    assert np.abs((got[0] + got[1]) / (L / n) - 1.0).max() < (1e-5 if prec == F32 else 1e-12)
+    ens.close()
