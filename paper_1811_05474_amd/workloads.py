@@ -62,6 +62,9 @@ WORKLOADS = {
     # species are the conservative components C1, C2 (no reaction term)
     "interface1d_l50": Workload("interface1d_l50", 1, 2000, 2, 0.5, 0.1, 100, 3.0, 1.0, 6000,
                                 react=None, box_hi=(50.0, 1.0, 1.0), n_real=75, init="interface"),
+    # the 2-D verification problem: 80 x 80 box, interface at x = 40
+    "interface2d_l80": Workload("interface2d_l80", 2, 20000, 2, 0.5, 0.1, 100, 3.0, 1.0, 9000,
+                                react=None, box_hi=(80.0, 80.0, 1.0), n_real=8, init="interface"),
     # the same interface at x0 = 10 advected with v = 1 and longitudinal
     # dispersivity 1 (Eq. 2 plus the transfer): the front reaches x = 20 at t = 10
     "advect1d_l50": Workload("advect1d_l50", 1, 2000, 2, 0.5, 0.1, 100, 3.0, 1.0, 8000,

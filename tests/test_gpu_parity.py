@@ -710,3 +710,30 @@ def test_advected_interface_follows_the_shifted_erfc(prec):
     # the components stay complementary
     assert np.abs((got[0] + got[1]) / (L / n) - 1.0).max() < (1e-5 if prec == F32 else 1e-12)
     ens.close()
+
+
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_interface2d_l80_matches_erfc(prec):
+    from scipy.special import erfc
+    w = W.WORKLOADS["interface2d_l80"]
+    L, n, R = w.box_hi[0], w.n, w.n_real
+    x, M, sizes, _ = W.make_inputs(w)
+    ens = make(dim=2, react=None, rw=w.rw_ratio, prec=prec, seed=w.seed, box_hi=w.box_hi)
+    ens.init(sizes, x, M)
+    # the first steps replayed against the oracle (realisation 0)
+    xcur, mcur = (f32(x[:n]), f32(M[:, :n])) if prec == F32 else (x[:n], M[:, :n])
+    for step in range(2):
+        ens.step(w.dt, w.D, 1)
+        pos, got = ens.positions()[:n], ens.masses()[:, :n]
+        walked = oracle.walk(xcur, np.arange(n), w.seed, step, w.D, w.dt, (0, 0), (L, L))
+        assert np.abs(pos - walked).max() < (2e-4 if prec == F32 else 1e-11)
+        ref = oracle.transfer(pos, mcur, w.D, w.dt, kappa=3.0, prec=32 if prec == F32 else 64, react=None)
+        assert normerr(got, ref) < (1e-5 if prec == F32 else 1e-12)
+        xcur, mcur = pos, got
+    ens.step(w.dt, w.D, w.steps - 2)
+    pos, got = ens.positions(), ens.masses()
+    ds = L * L / n
+    exact = 0.5 * erfc((0.5 * L - pos[:, 0]) / math.sqrt(4 * (2 * w.D) * w.steps * w.dt))
+    per_real = np.sqrt(np.mean(((got[0] / ds - exact) ** 2).reshape(R, n), axis=1))
+    assert per_real.max() < 0.025 and per_real.mean() < 0.02, per_real
+    ens.close()

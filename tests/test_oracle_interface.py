@@ -53,3 +53,24 @@ def test_interface_error_falls_with_particle_number():
     small = np.mean([rmse_after(500, 0.5, 0.5, 6200 + r) for r in range(6)])
     large = np.mean([rmse_after(4000, 0.5, 0.5, 6200 + r) for r in range(6)])
     assert large < small
+
+
+def rmse_2d(D_transfer, D_walk, seed, n=20000):
+    L = 80.0
+    x, M = W.interface(n, 2, L, seed)
+    ds = L * L / n
+    ids = np.arange(n, dtype=np.uint32)
+    for s in range(STEPS):
+        if D_walk > 0:
+            x = oracle.walk(x, ids, seed, s, D_walk, DT, (0.0, 0.0), (L, L))
+        M = oracle.transfer(x, M, D_transfer, DT, kappa=3.0, prec=64, react=None)
+    exact = 0.5 * erfc((0.5 * L - x[:, 0]) / math.sqrt(4 * 1.0 * STEPS * DT))
+    return math.sqrt(np.mean((M[0] / ds - exact) ** 2))
+
+
+def test_interface_2d_80x80():
+    # the 2-D form of the verification problem (80 x 80 box, interface at
+    # x = 40): the profile across the interface is the same erfc
+    assert rmse_2d(0.5, 0.5, 9000) < 0.02
+    assert rmse_2d(1.0, 0.0, 9000) < 0.02       # kernel width in 2-D
+    assert rmse_2d(0.5, 0.0, 9000) > 0.03       # missing walk
