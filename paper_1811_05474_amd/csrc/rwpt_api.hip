@@ -458,7 +458,6 @@ static PairArgs pair_args(rwpt_ctx* c) {
   PairArgs a;
   memset(&a, 0, sizeof(a));
   a.pos = c->pos0.p;
-  a.cap = c->cap;
   a.mass_in = mass_buf(c, c->mcur).p;
   a.mass_out = mass_buf(c, c->mcur ^ 1).p;
   a.q_in = c->q.p;
@@ -494,7 +493,7 @@ static rwpt_status enqueue_sort(rwpt_ctx* c, bool walk, bool move_mass) {
   const int32_t n = (int32_t)c->N;
   {
     PhaseScope ps(c, PH_WALK_KEY);
-    HIPCHK(c, launch_walk_key(fp64, c->dim, c->pos0.p, c->pos1.p, c->cap, c->id.as<uint32_t>(), n,
+    HIPCHK(c, launch_walk_key(fp64, c->dim, c->pos0.p, c->pos1.p, c->id.as<uint32_t>(), n,
                               c->d_rp.as<RealParams>(), c->d_real_start.as<int64_t>(), c->n_real,
                               c->step_ctr.as<uint64_t>(), c->cfg.seed, walk ? 1 : 0,
                               c->cell_count.as<uint32_t>(), c->key.as<uint32_t>(),
@@ -515,7 +514,7 @@ static rwpt_status enqueue_sort(rwpt_ctx* c, bool walk, bool move_mass) {
     PhaseScope ps(c, PH_CANON);
     HIPCHK(c, launch_canon(fp64, c->dim, n, c->tmp_src.as<uint32_t>(), c->tmp_id.as<uint32_t>(),
                            c->tmp_key.as<uint32_t>(), c->cell_start.as<uint32_t>(), c->pos1.p, c->pos0.p,
-                           c->cap, mass_buf(c, c->mcur).p, mass_buf(c, c->mcur ^ 1).p, c->S,
+                           mass_buf(c, c->mcur).p, mass_buf(c, c->mcur ^ 1).p, c->S,
                            c->id.as<uint32_t>(), c->skey.as<uint32_t>(),
                            move_mass ? nullptr : c->src_of.as<uint32_t>(), c->stream));
   }

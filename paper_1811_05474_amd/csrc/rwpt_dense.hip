@@ -74,7 +74,7 @@ __device__ __forceinline__ float box_dist2(const float* a, const float* b) {
 
 // Bounding box (min, max per axis) of every column tile of kColTile particles.
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_tile_bbox(const float* __restrict__ pos, int64_t cap, int32_t n,
+__global__ __launch_bounds__(kBlock) void k_tile_bbox(const float* __restrict__ pos, int32_t n,
                                                       float* __restrict__ bbox) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int j0 = t * kColTile;
@@ -120,8 +120,7 @@ __device__ __forceinline__ void load_box(const float* __restrict__ bbox, int t, 
 
 // Pass 1: one lane per row, column tiles broadcast through scalar loads.
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_dense_rowsum(const float* __restrict__ pos, const int64_t cap,
-                                                         const int32_t n, const float* __restrict__ bbox,
+__global__ __launch_bounds__(kBlock) void k_dense_rowsum(const float* __restrict__ pos, const int32_t n, const float* __restrict__ bbox,
                                                          const int32_t ntile, const float escale,
                                                          const float skip_s2, double* __restrict__ r_out,
                                                          float* __restrict__ q_out) {
@@ -345,8 +344,8 @@ hipError_t launch_dense_step(int dim, const DenseArgs& a, hipStream_t s) {
   const dim3 gprep((unsigned)((a.cap + kBlock - 1) / kBlock));
   auto go = [&](auto d) {
     constexpr int D = decltype(d)::value;
-    hipLaunchKernelGGL((k_tile_bbox<D>), gbox, b, 0, s, a.pos, a.cap, n, a.bbox);
-    hipLaunchKernelGGL((k_dense_rowsum<D>), gsum, b, 0, s, a.pos, a.cap, n, a.bbox, ntile, a.escale,
+    hipLaunchKernelGGL((k_tile_bbox<D>), gbox, b, 0, s, a.pos, n, a.bbox);
+    hipLaunchKernelGGL((k_dense_rowsum<D>), gsum, b, 0, s, a.pos, n, a.bbox, ntile, a.escale,
                        a.skip_s2, a.r, a.q);
     hipLaunchKernelGGL(k_dense_prep_b, gprep, b, 0, s, a.mass_in, a.q, a.cap, n, a.S, a.norm, NC, a.bparts);
     if (a.ncb == 1)

@@ -46,7 +46,6 @@ struct Tile {
 // binary64 according to the kernel instantiation.
 struct PairArgs {
   const void* pos;         // [cap][PS] particle-major (PS = 1, 2, 4), cell-sorted
-  int64_t cap;             // particle capacity of the position / mass arrays
   const void* mass_in;     // [cap][SP] particle-major (SP = 2, 4, 8 species slots)
   void* mass_out;          // [cap][SP]
   const void* q_in;        // 1 / r_i for the symmetric normalisation, [cap]

@@ -24,7 +24,7 @@ constexpr int kScanChunk = kBlock * kScanItems;
 
 // Random walk + reflection (optional) and cell key / in-cell slot of every particle.
 // pos_in/pos_out may not alias.
-hipError_t launch_walk_key(int fp64, int dim, const void* pos_in, void* pos_out, int64_t cap,
+hipError_t launch_walk_key(int fp64, int dim, const void* pos_in, void* pos_out,
                            const uint32_t* id, int32_t n, const RealParams* rp,
                            const int64_t* real_start, int32_t n_real, const uint64_t* step_ctr,
                            uint64_t seed, int32_t do_walk, uint32_t* cell_count, uint32_t* key,
@@ -47,7 +47,7 @@ hipError_t launch_scatter(int32_t n, const uint32_t* key, const uint32_t* slot,
 hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
                         const uint32_t* tmp_id, const uint32_t* tmp_key,
                         const uint32_t* cell_start, const void* pos_in, void* pos_out,
-                        int64_t cap, const void* mass_in, void* mass_out, int32_t S,
+                        const void* mass_in, void* mass_out, int32_t S,
                         uint32_t* id_out, uint32_t* skey, uint32_t* src_out, hipStream_t s);
 
 // Species slots per particle the mass arrays hold for S species: the kernels

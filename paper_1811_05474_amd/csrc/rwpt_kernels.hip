@@ -164,7 +164,7 @@ __device__ __forceinline__ double escale_of<double>(const RealParams& P) { retur
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_walk_key(
-    const T* __restrict__ pos_in, T* __restrict__ pos_out, int64_t cap,
+    const T* __restrict__ pos_in, T* __restrict__ pos_out,
     const uint32_t* __restrict__ id, int32_t n, const RealParams* __restrict__ rp,
     const int64_t* __restrict__ real_start, int32_t n_real, const uint64_t* __restrict__ step_ctr,
     uint64_t seed, int32_t do_walk, uint32_t* __restrict__ cell_count, uint32_t* __restrict__ key_out,
@@ -366,8 +366,8 @@ template <typename T, int DIM, int SMAX, bool MOVE>
 __global__ __launch_bounds__(kBlock) void k_canon(
     int32_t n, const uint32_t* __restrict__ tmp_src, const uint32_t* __restrict__ tmp_id,
     const uint32_t* __restrict__ tmp_key, const uint32_t* __restrict__ cell_start,
-    const T* __restrict__ pos_in, T* __restrict__ pos_out, int64_t cap, const T* __restrict__ mass_in,
-    T* __restrict__ mass_out, int32_t S, uint32_t* __restrict__ id_out, uint32_t* __restrict__ skey,
+    const T* __restrict__ pos_in, T* __restrict__ pos_out, const T* __restrict__ mass_in,
+    T* __restrict__ mass_out, uint32_t* __restrict__ id_out, uint32_t* __restrict__ skey,
     uint32_t* __restrict__ src_out) {
   const int e = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (e >= n) return;
@@ -534,7 +534,7 @@ __device__ __forceinline__ void halve_sum(double (&v)[NV], int& idx, int& real, 
 template <typename T, int SMAX, int G>
 __device__ __forceinline__ void exchange_epilogue(const RealParams& P, bool sym, const double acc[SMAX],
                                                   double racc, const T Mi[SMAX], bool writer, int32_t i,
-                                                  T* __restrict__ mout, int64_t cap, int S, int react_a,
+                                                  T* __restrict__ mout, int S, int react_a,
                                                   int react_b, double* __restrict__ audit_part) {
   double tot[SMAX + 1];
 #pragma unroll
@@ -597,7 +597,7 @@ __device__ __forceinline__ void exchange_epilogue(const RealParams& P, bool sym,
 // the normalisation of the co-location weights.
 template <typename T, int DIM, int LOG2L>
 __global__ __launch_bounds__(kBlock) void k_rowsum(
-    const T* __restrict__ pos, const int64_t cap, const uint32_t* __restrict__ skey,
+    const T* __restrict__ pos, const uint32_t* __restrict__ skey,
     const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles, const int32_t ntiles,
     const RealParams* __restrict__ rp, const StencilRow* __restrict__ st, double* __restrict__ r_out,
     T* __restrict__ q_out) {
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(
 // row normalisation: dM_i = 1/2 (sum_j w_ij (M_j - M_i)) / r_i.
 template <typename T, int DIM, int SMAX, int LOG2L>
 __global__ __launch_bounds__(kBlock) void k_exchange(
-    const T* __restrict__ pos, const int64_t cap, const T* __restrict__ min_, T* __restrict__ mout,
+    const T* __restrict__ pos, const T* __restrict__ min_, T* __restrict__ mout,
     const T* __restrict__ q, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ cell_start,
     const Tile* __restrict__ tiles, const int32_t ntiles, const RealParams* __restrict__ rp,
     const StencilRow* __restrict__ st, const int32_t S, const int32_t react_a, const int32_t react_b,
@@ -692,7 +692,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
         for (int s = 0; s < SMAX; ++s) accr[s] = (T)0;
         const uint32_t len = je - jb, nblk = len / (L * kUnroll);
         uint32_t j = jb + tl.gl;
-        // species rows S..SMAX-1 exist and hold zeros, so no guard is needed
+        // species slots S..SMAX-1 exist and hold zeros, so no guard is needed
         auto eval = [&](const T xj[DIM], T qj, const T mj[SMAX]) {
           const T s2 = sep2v<T, DIM>(xi, xj);
           T w = kweight(s2, esc);
@@ -783,7 +783,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
     for (int s = 0; s < SMAX; ++s) acc[s] += __shfl_xor(acc[s], off);
     racc += __shfl_xor(racc, off);
   }
-  exchange_epilogue<T, SMAX, G>(P, sym, acc, racc, Mi, tl.gl == 0 && tl.valid, tl.i, mout, cap, S, react_a,
+  exchange_epilogue<T, SMAX, G>(P, sym, acc, racc, Mi, tl.gl == 0 && tl.valid, tl.i, mout, S, react_a,
                                 react_b, audit_part);
 }
 
@@ -901,7 +901,7 @@ __device__ __forceinline__ void for_tile_chunks(const RealParams& P, const Stenc
 
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
-    const float* __restrict__ pos, const int64_t cap, const uint32_t* __restrict__ skey,
+    const float* __restrict__ pos, const uint32_t* __restrict__ skey,
     const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles, const int32_t ntiles,
     const RealParams* __restrict__ rp, const StencilRow* __restrict__ st, double* __restrict__ r_out,
     float* __restrict__ q_out) {
@@ -952,7 +952,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
 
 template <int DIM, int SMAX>
 __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
-    const float* __restrict__ pos, const int64_t cap, const float* __restrict__ min_, float* __restrict__ mout,
+    const float* __restrict__ pos, const float* __restrict__ min_, float* __restrict__ mout,
     const float* __restrict__ q, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ cell_start,
     const Tile* __restrict__ tiles, const int32_t ntiles, const RealParams* __restrict__ rp,
     const StencilRow* __restrict__ st, const int32_t S, const int32_t react_a, const int32_t react_b,
@@ -981,7 +981,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
       load_pos<float, DIM>(pos, j, xj);
       if (!has) xj[0] = 3.0e38f;  // outside the cutoff, weight 0
       const float qj = q[j];
-      // species rows S..SMAX-1 exist and hold zeros, so no guard is needed
+      // species slots S..SMAX-1 exist and hold zeros, so no guard is needed
       load_mass<float, SMAX>(min_, j, mj);
       float accr[SMAX];
 #pragma unroll
@@ -1037,15 +1037,17 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
     for (int s = 0; s < SMAX; ++s) acc[s] += __shfl_xor(acc[s], off);
     racc += __shfl_xor(racc, off);
   }
-  exchange_epilogue<float, SMAX, G>(P, sym, acc, racc, Mi, tl.gl == 0 && tl.valid, tl.i, mout, cap, S,
+  exchange_epilogue<float, SMAX, G>(P, sym, acc, racc, Mi, tl.gl == 0 && tl.valid, tl.i, mout, S,
                                     react_a, react_b, audit_part);
 }
 
 // ---------------------------------------------------------------------------
-// Pair kernels with private candidate lists: one lane per particle, each lane
-// walks its own stencil rows [cx - rx, cx + rx] around its own cell.  Suited
-// to sparse neighbourhoods, where the candidate union of a shared tile would
-// be mostly misses.
+// Pair kernels with private candidate lists: one lane per particle, for
+// sparse neighbourhoods, where the candidate union of a shared tile would be
+// mostly misses.  The row-sum pass takes each particle's own cutoff box and
+// keeps its neighbours in a per-wave cache; the exchange reads the cache, and
+// lanes that overflowed it walk the stencil rows [cx - rx, cx + rx] around
+// their cell (for_own_rows).
 // ---------------------------------------------------------------------------
 
 template <typename T, int DIM, typename RowFn>
@@ -1099,9 +1101,8 @@ __device__ __forceinline__ int cell_of(const RealParams& P, int k, double v) {
 
 template <typename T, int DIM, bool IND>
 __global__ __launch_bounds__(kBlock) void k_rowsum_priv(
-    const T* __restrict__ pos, const int64_t cap, const uint32_t* __restrict__ skey,
-    const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles, const int32_t ntiles,
-    const RealParams* __restrict__ rp, const StencilRow* __restrict__ st, double* __restrict__ r_out,
+    const T* __restrict__ pos, const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles,
+    const int32_t ntiles, const RealParams* __restrict__ rp, double* __restrict__ r_out,
     T* __restrict__ q_out, uint16_t* __restrict__ nb_meta, uint32_t* __restrict__ nb_idx,
     T* __restrict__ nb_w, uint32_t* __restrict__ nb_src, const uint32_t* __restrict__ src_of) {
   constexpr int RB = PrivBatch<DIM>::kRowBatch, CB = PrivBatch<DIM>::kCandBatch;
@@ -1228,7 +1229,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_priv(
 // normalisation comes from the row-sum pass.
 template <typename T, int DIM, int SMAX, bool IND>
 __global__ __launch_bounds__(kBlock) void k_exchange_priv(
-    const T* __restrict__ pos, const int64_t cap, const T* __restrict__ min_, T* __restrict__ mout,
+    const T* __restrict__ pos, const T* __restrict__ min_, T* __restrict__ mout,
     const T* __restrict__ q, const double* __restrict__ r_in, const uint32_t* __restrict__ skey,
     const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles, const int32_t ntiles,
     const RealParams* __restrict__ rp, const StencilRow* __restrict__ st, const int32_t S,
@@ -1300,7 +1301,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
           const T s2 = sep2<T, DIM>(xi, pos, j);
           if (!(s2 <= rc2)) continue;  // sparse: most candidates miss, skip their loads
           const T w = kweight(s2, esc);
-          // species rows S..SMAX-1 exist and hold zeros
+          // species slots S..SMAX-1 exist and hold zeros
           const T p = sym ? w * (qi + q[j]) : w;
           rr += w;
           T mj[SMAX];
@@ -1314,7 +1315,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
       });
     }
   }
-  exchange_epilogue<T, SMAX, 64>(P, sym, acc, racc, Mi, tl.valid, tl.i, mout, cap, S, react_a, react_b,
+  exchange_epilogue<T, SMAX, 64>(P, sym, acc, racc, Mi, tl.valid, tl.i, mout, S, react_a, react_b,
                                  audit_part);
 }
 
@@ -1327,7 +1328,6 @@ __global__ __launch_bounds__(kBlock) void k_count(PairArgs a) {
   if (!tile_lane_setup<LOG2L>(a.tiles, a.ntiles, tl, tile)) return;
   const RealParams& P = a.rp[tile.real];
   const T* __restrict__ pos = (const T*)a.pos;
-  const int64_t cap = a.cap;
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   T xi[DIM];
   load_pos<T, DIM>(pos, ii, xi);
@@ -1373,7 +1373,6 @@ __global__ __launch_bounds__(kBlock) void k_nbr(PairArgs a) {
   if (!tile_lane_setup<LOG2L>(a.tiles, a.ntiles, tl, tile)) return;
   const RealParams& P = a.rp[tile.real];
   const T* __restrict__ pos = (const T*)a.pos;
-  const int64_t cap = a.cap;
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   T xi[DIM];
   load_pos<T, DIM>(pos, ii, xi);
@@ -1510,7 +1509,7 @@ __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ par
 
 static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-hipError_t launch_walk_key(int fp64, int dim, const void* pos_in, void* pos_out, int64_t cap,
+hipError_t launch_walk_key(int fp64, int dim, const void* pos_in, void* pos_out,
                            const uint32_t* id, int32_t n, const RealParams* rp,
                            const int64_t* real_start, int32_t n_real, const uint64_t* step_ctr,
                            uint64_t seed, int32_t do_walk, uint32_t* cell_count, uint32_t* key,
@@ -1518,7 +1517,7 @@ hipError_t launch_walk_key(int fp64, int dim, const void* pos_in, void* pos_out,
   if (n <= 0) return hipSuccess;
   const dim3 g(blocks_for(n)), b(kBlock);
 #define RWPT_WK(T, D)                                                                             \
-  hipLaunchKernelGGL((k_walk_key<T, D>), g, b, 0, s, (const T*)pos_in, (T*)pos_out, cap, id, n, rp, \
+  hipLaunchKernelGGL((k_walk_key<T, D>), g, b, 0, s, (const T*)pos_in, (T*)pos_out, id, n, rp, \
                      real_start, n_real, step_ctr, seed, do_walk, cell_count, key, slot)
   if (fp64) {
     if (dim == 1) RWPT_WK(double, 1);
@@ -1555,7 +1554,7 @@ hipError_t launch_scatter(int32_t n, const uint32_t* key, const uint32_t* slot,
 hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
                         const uint32_t* tmp_id, const uint32_t* tmp_key,
                         const uint32_t* cell_start, const void* pos_in, void* pos_out,
-                        int64_t cap, const void* mass_in, void* mass_out, int32_t S,
+                        const void* mass_in, void* mass_out, int32_t S,
                         uint32_t* id_out, uint32_t* skey, uint32_t* src_out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const dim3 g(blocks_for(n)), b(kBlock);
@@ -1569,12 +1568,12 @@ hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
   do {                                                                                          \
     if (src_out)                                                                                \
       hipLaunchKernelGGL((k_canon<T, D, SM, false>), g, b, 0, s, n, tmp_src, tmp_id, tmp_key,     \
-                         cell_start, (const T*)pos_in, (T*)pos_out, cap, (const T*)mass_in,     \
-                         (T*)mass_out, S, id_out, skey, src_out);                               \
+                         cell_start, (const T*)pos_in, (T*)pos_out, (const T*)mass_in,          \
+                         (T*)mass_out, id_out, skey, src_out);                               \
     else                                                                                        \
       hipLaunchKernelGGL((k_canon<T, D, SM, true>), g, b, 0, s, n, tmp_src, tmp_id, tmp_key,      \
-                         cell_start, (const T*)pos_in, (T*)pos_out, cap, (const T*)mass_in,     \
-                         (T*)mass_out, S, id_out, skey, src_out);                               \
+                         cell_start, (const T*)pos_in, (T*)pos_out, (const T*)mass_in,          \
+                         (T*)mass_out, id_out, skey, src_out);                               \
   } while (0)
   if (fp64) {
     if (dim == 1) RWPT_CN(double, 1);
@@ -1629,8 +1628,8 @@ hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStr
       using T = decltype(t);
       constexpr int D = decltype(d)::value;
 #define RWPT_RSP_ARGS                                                                                 \
-  (const T*)a.pos, a.cap, a.skey, a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (T*)a.q_out,     \
-      a.nb_meta, a.nb_idx, (T*)a.nb_w, a.nb_src, a.src_of
+  (const T*)a.pos, a.cell_start, a.tiles, a.ntiles, a.rp, a.r_out, (T*)a.q_out, a.nb_meta, a.nb_idx, \
+      (T*)a.nb_w, a.nb_src, a.src_of
       if (a.indirect) hipLaunchKernelGGL((k_rowsum_priv<T, D, true>), g, b, 0, s, RWPT_RSP_ARGS);
       else hipLaunchKernelGGL((k_rowsum_priv<T, D, false>), g, b, 0, s, RWPT_RSP_ARGS);
 #undef RWPT_RSP_ARGS
@@ -1638,7 +1637,7 @@ hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStr
   }
   if (!fp64 && log2l == 2) {
     auto go = [&](auto d) {
-      hipLaunchKernelGGL((k_rowsum_dpp<decltype(d)::value>), g, b, 0, s, (const float*)a.pos, a.cap, a.skey,
+      hipLaunchKernelGGL((k_rowsum_dpp<decltype(d)::value>), g, b, 0, s, (const float*)a.pos, a.skey,
                          a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (float*)a.q_out);
     };
     if (dim == 1) go(IC<1>{});
@@ -1650,7 +1649,7 @@ hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStr
   return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
     using T = decltype(t);
     hipLaunchKernelGGL((k_rowsum<T, decltype(d)::value, decltype(l)::value>), g, b, 0, s, (const T*)a.pos,
-                       a.cap, a.skey, a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (T*)a.q_out);
+                       a.skey, a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (T*)a.q_out);
   });
 }
 
@@ -1663,7 +1662,7 @@ hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipS
       using T = decltype(t);
       constexpr int D = decltype(d)::value;
 #define RWPT_EXP_ARGS                                                                                  \
-  (const T*)a.pos, a.cap, (const T*)a.mass_in, (T*)a.mass_out, (const T*)a.q_in, a.r_out, a.skey,        \
+  (const T*)a.pos, (const T*)a.mass_in, (T*)a.mass_out, (const T*)a.q_in, a.r_out, a.skey,        \
       a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.S, a.react_a, a.react_b, a.norm, a.audit_part,      \
       a.nb_meta, a.nb_idx, (const T*)a.nb_w, a.nb_src, a.src_of
       auto go = [&](auto sm, auto ind) {
@@ -1684,7 +1683,7 @@ hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipS
     auto go = [&](auto d) {
       constexpr int D = decltype(d)::value;
 #define RWPT_EXD_ARGS                                                                                  \
-  (const float*)a.pos, a.cap, (const float*)a.mass_in, (float*)a.mass_out, (const float*)a.q_in, a.skey, \
+  (const float*)a.pos, (const float*)a.mass_in, (float*)a.mass_out, (const float*)a.q_in, a.skey, \
       a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.S, a.react_a, a.react_b, a.norm, a.audit_part
       if (a.S <= 2) hipLaunchKernelGGL((k_exchange_dpp<D, 2>), g, b, 0, s, RWPT_EXD_ARGS);
       else if (a.S <= 4) hipLaunchKernelGGL((k_exchange_dpp<D, 4>), g, b, 0, s, RWPT_EXD_ARGS);
@@ -1701,7 +1700,7 @@ hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipS
     using T = decltype(t);
     constexpr int D = decltype(d)::value, L = decltype(l)::value;
 #define RWPT_EX_ARGS                                                                          \
-  (const T*)a.pos, a.cap, (const T*)a.mass_in, (T*)a.mass_out, (const T*)a.q_in, a.skey, a.cell_start, \
+  (const T*)a.pos, (const T*)a.mass_in, (T*)a.mass_out, (const T*)a.q_in, a.skey, a.cell_start, \
       a.tiles, a.ntiles, a.rp, a.st, a.S, a.react_a, a.react_b, a.norm, a.audit_part
     if (a.S <= 2) hipLaunchKernelGGL((k_exchange<T, D, 2, L>), g, b, 0, s, RWPT_EX_ARGS);
     else if (a.S <= 4) hipLaunchKernelGGL((k_exchange<T, D, 4, L>), g, b, 0, s, RWPT_EX_ARGS);
