@@ -183,12 +183,17 @@ def cpu_baseline(W, w, unordered_pairs_per_step, budget_s=15.0):
     }
 
 
+# the device code and the host code that picks its launch shapes; the counter
+# summaries in profiles/ record the SHA-256 of their concatenation, in this order
+DEVICE_SOURCES = ("rwpt_device.h", "rwpt_layout.h", "rwpt_kernels.h", "rwpt_kernels.hip", "rwpt_dense.hip",
+                  "rwpt_api.hip")
+
+
 def measured_traffic(kernel_tag: str):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     summary, or None when the kernel source changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "%s.txt" % kernel_tag)
-    src = os.path.join(ROOT, "paper_1811_05474_amd", "csrc", "rwpt_kernels.hip")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -196,8 +201,10 @@ def measured_traffic(kernel_tag: str):
         if ":" in line and not line.startswith(" "):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("kernel_source_sha256") != sha:
+    digest = hashlib.sha256()
+    for name in DEVICE_SOURCES:
+        digest.update(open(os.path.join(ROOT, "paper_1811_05474_amd", "csrc", name), "rb").read())
+    if fields.get("kernel_source_sha256") != digest.hexdigest():
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
