@@ -132,6 +132,12 @@ def run_path(rwpt, W, w, precision, steps, warmup, tile_lanes, profile=True):
                              "us_avg": (1e3 * v[0] / v[1]) if v[1] else 0.0} for k, v in prof.items() if v[1]}
     out["audit"] = ens.audit().sum(axis=0).tolist()
     out["tiling"] = rwpt.rwpt_get_tiling(ens.ctx)
+    if profile and precision == rwpt.RWPT_FP32 and out["tiling"][0] == 4 and "rowsum" in out.get("phases", {}):
+        # attainable rates of the row-broadcast kernels' inner loops on this
+        # device, from register-only kernels running the same per-candidate code
+        out["probe"] = {k: ens.probe_rate(v) for k, v in (
+            ("fma", rwpt.RWPT_PROBE_FMA), ("exp", rwpt.RWPT_PROBE_EXP),
+            ("rowsum", rwpt.RWPT_PROBE_ROWSUM), ("exchange", rwpt.RWPT_PROBE_EXCHANGE))}
     ens.close()
     return out
 
@@ -185,8 +191,8 @@ def cpu_baseline(W, w, unordered_pairs_per_step, budget_s=15.0):
 
 # the device code and the host code that picks its launch shapes; the counter
 # summaries in profiles/ record the SHA-256 of their concatenation, in this order
-DEVICE_SOURCES = ("rwpt_device.h", "rwpt_layout.h", "rwpt_kernels.h", "rwpt_kernels.hip", "rwpt_dense.hip",
-                  "rwpt_api.hip")
+DEVICE_SOURCES = ("rwpt_device.h", "rwpt_layout.h", "rwpt_pairstep.h", "rwpt_kernels.h", "rwpt_kernels.hip",
+                  "rwpt_dense.hip", "rwpt_api.hip")
 
 
 def measured_traffic(kernel_tag: str):
@@ -289,6 +295,20 @@ def main():
     }
     if dense:
         roofline["ordered_pairs_evaluated_per_launch"] = alg_pairs
+    valu_probe = None
+    if "probe" in r32:
+        pr = r32["probe"]
+        ev = r32["evaluations_per_step"]
+        valu_probe = {
+            "scope": "row-broadcast pair kernels: candidate evaluations/s against a register-only kernel "
+                     "running the same per-candidate code at full occupancy (rwpt_probe_rate)",
+            "fma_lane_ops_per_s": pr["fma"],
+            "exp_lane_ops_per_s": pr["exp"],
+        }
+        for k in ("rowsum", "exchange"):
+            got = ev / (r32["phases"][k]["us_avg"] * 1e-6)
+            valu_probe[k] = {"achieved": got, "attainable": pr[k], "unit": "evaluations/s",
+                             "frac": got / pr[k]}
     step_bytes = step_bytes_per_particle(w.dim, w.n_species, 4) * n_total
     step_gbps = step_bytes / (r32["ms_per_step"] * 1e-3) / 1e9
     step_roofline = {
@@ -329,6 +349,7 @@ def main():
         "phases_us": {k: round(v["us_avg"], 2) for k, v in r32["phases"].items()},
         "roofline": roofline,
         "step_roofline": step_roofline,
+        "valu_probe": valu_probe,
     }
     if r64 is not None:
         m32, m64 = r32["masses"], r64["masses"]

@@ -208,6 +208,27 @@ typedef struct rwpt_stats_t {
 } rwpt_stats_t;
 rwpt_status rwpt_stats(rwpt_ctx *ctx, rwpt_stats_t *out);
 
+/* Attainable instruction rates of this device for the pair kernels (not a
+ * step of the method: a measurement).  Runs a register-only kernel at full
+ * occupancy (8 waves per SIMD) on the context's device and stream and returns
+ * the rate in *per_s (synchronous; the state is not changed):
+ *   RWPT_PROBE_FMA       independent binary32 FMAs, lane operations per second;
+ *   RWPT_PROBE_EXP       binary32 exp2 (v_exp_f32), lane operations per second;
+ *   RWPT_PROBE_ROWSUM    candidate evaluations per second of the row-sum inner
+ *                        loop of the row-broadcast tiling (tile_lanes = 4):
+ *                        distance, cutoff predicate, weight exp(-s^2/sigma^2)
+ *                        of Eq. (3) and the row sum r_i, for the context's dim;
+ *   RWPT_PROBE_EXCHANGE  the same for the symmetric exchange inner loop (weight,
+ *                        P_ij of the symmetric normalisation and the products
+ *                        of Eq. (4) for the context's species count).
+ * The row-sum and exchange probes execute the kernels' own per-candidate code
+ * on operands held in registers (no loads, no neighbour search), so a kernel's
+ * measured evaluation rate over this figure is the fraction of its attainable
+ * inner-loop rate.  Errors: RWPT_EINVAL (NULL ctx or per_s, unknown kind),
+ * RWPT_EDEVICE / RWPT_ENOMEM from the runtime. */
+enum { RWPT_PROBE_FMA = 0, RWPT_PROBE_EXP = 1, RWPT_PROBE_ROWSUM = 2, RWPT_PROBE_EXCHANGE = 3 };
+rwpt_status rwpt_probe_rate(rwpt_ctx *ctx, int32_t kind, double *per_s);
+
 /* Current tiling: tile_lanes and the per-axis cell refinement in use. */
 rwpt_status rwpt_get_tiling(rwpt_ctx *ctx, int32_t *tile_lanes, double *cell_refine3);
 

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librwpt.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["rwpt_kernels.hip", "rwpt_dense.hip", "rwpt_api.hip"]
+SOURCES = ["rwpt_kernels.hip", "rwpt_dense.hip", "rwpt_probe.hip", "rwpt_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1137,6 +1137,51 @@ rwpt_status rwpt_stats(rwpt_ctx* c, rwpt_stats_t* out) {
   return RWPT_OK;
 }
 
+// Timed launches of one probe kernel: one untimed launch, then `timed`
+// launches between two events on the context's stream.
+static hipError_t probe_time(rwpt_ctx* c, int kind, int blocks, int reps, int timed, float* out, float* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  // cutoff 1 on the probe's lattice of spacing 1/8 in [0, 2); weight exp(-s^2)
+  const float rc2 = 1.0f, esc = -1.4426950408889634f, h = 1.0f;
+  const int slots = species_slots(c->cfg.n_species);
+  if (e == hipSuccess) e = launch_probe(kind, c->dim, slots, blocks, reps, rc2, esc, h, out, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+  for (int t = 0; t < timed && e == hipSuccess; ++t)
+    e = launch_probe(kind, c->dim, slots, blocks, reps, rc2, esc, h, out, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  return e;
+}
+
+rwpt_status rwpt_probe_rate(rwpt_ctx* c, int32_t kind, double* per_s) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  c->err.clear();
+  if (!per_s) return fail(c, RWPT_EINVAL, "per_s is NULL");
+  if (kind < PROBE_FMA || kind > PROBE_EXCHANGE) return fail(c, RWPT_EINVAL, "probe kind %d not in 0..3", kind);
+  rwpt_status st = ensure_device(c);
+  if (st != RWPT_OK) return st;
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  int cus = 0;
+  HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->cfg.device));
+  const int blocks = (cus > 0 ? cus : 1) * 8;  // 8 blocks of 4 waves per CU: 8 waves per SIMD
+  const int reps = (kind == PROBE_FMA || kind == PROBE_EXP) ? 500 : 1000;
+  const int timed = 3;
+  DevBuf out;
+  hipError_t e = out.ensure((size_t)blocks * probe_block() * sizeof(float));
+  float ms = 0.0f;
+  if (e == hipSuccess) e = probe_time(c, kind, blocks, reps, timed, out.as<float>(), &ms);
+  out.release();
+  HIPCHK(c, e);
+  if (!(ms > 0.0f)) return fail(c, RWPT_EDEVICE, "probe kind %d: non-positive elapsed time", kind);
+  *per_s = (double)blocks * probe_block() * (double)probe_ops_per_lane(kind, reps) * timed / (ms * 1e-3);
+  return RWPT_OK;
+}
+
 rwpt_status rwpt_get_tiling(rwpt_ctx* c, int32_t* tile_lanes, double* cell_refine3) {
   if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
   int lanes = c->cfg.tile_lanes ? c->cfg.tile_lanes : default_lanes(c->dim, c->N, c->cfg.precision == RWPT_FP64);

@@ -108,4 +108,15 @@ constexpr int64_t kDenseMaxN = (int64_t)1 << 17;
 inline int dense_ncb(int S, int norm) { return ((norm == 0 ? 2 * S + 2 : S + 1) + 15) / 16; }
 hipError_t launch_dense_step(int dim, const DenseArgs& a, hipStream_t s);
 
+// Instruction-rate probes (register-only kernels of rwpt_probe.hip): binary32
+// FMA, binary32 exp2, and the per-candidate code of the row-broadcast row-sum
+// and symmetric exchange kernels.  `reps` is iterations (FMA, exp) or chunks
+// of 16 candidates (row sum, exchange) per lane; out holds one float per
+// thread of the grid (blocks * probe_block()).
+enum ProbeKind { PROBE_FMA = 0, PROBE_EXP = 1, PROBE_ROWSUM = 2, PROBE_EXCHANGE = 3 };
+int probe_block();
+int64_t probe_ops_per_lane(int kind, int reps);
+hipError_t launch_probe(int kind, int dim, int slots, int blocks, int reps, float rc2, float esc, float h, float* out,
+                        hipStream_t s);
+
 }  // namespace rwpt

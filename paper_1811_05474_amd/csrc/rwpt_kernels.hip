@@ -16,6 +16,7 @@
 
 #include "rwpt_kernels.h"
 #include "rwpt_layout.h"
+#include "rwpt_pairstep.h"
 
 namespace rwpt {
 
@@ -136,14 +137,6 @@ constexpr int kUnroll = 4;
 // binary32 row partials are added into the binary64 accumulators at least
 // every kFlushBlocks * kUnroll candidates per lane
 constexpr uint32_t kFlushBlocks = 64;
-
-// Co-location weight exp(-s2 / sigma^2) (Eq. 3 without prefactor): binary32
-// uses the hardware exp2 with the scale -log2(e)/sigma^2; binary64 uses the
-// library exp.
-__device__ __forceinline__ float kweight(float s2, float escale) {
-  return __builtin_amdgcn_exp2f(s2 * escale);
-}
-__device__ __forceinline__ double kweight(double s2, double escale) { return exp(s2 * escale); }
 
 template <typename T>
 __device__ __forceinline__ T rc2_of(const RealParams& P);
@@ -798,26 +791,6 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
 // instruction.  Each particle sees all 64 candidates across its four lanes.
 // ---------------------------------------------------------------------------
 
-template <int K>
-__device__ __forceinline__ float rshare(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + K, 0xf,
-                                                               0xf, false));
-}
-
-template <int K, int N>
-struct Steps {
-  template <typename F>
-  __device__ __forceinline__ static void run(F&& f) {
-    f(std::integral_constant<int, K>{});
-    Steps<K + 1, N>::run(f);
-  }
-};
-template <int N>
-struct Steps<N, N> {
-  template <typename F>
-  __device__ __forceinline__ static void run(F&&) {}
-};
-
 // Wave-uniform cursor over the non-empty stencil rows of one segment.
 struct RowCursor {
   int r;            // next stencil entry to examine
@@ -920,23 +893,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
       float xj[DIM];
       load_pos<float, DIM>(pos, j, xj);
       if (!has) xj[0] = 3.0e38f;  // s^2 overflows to +inf: outside the cutoff, weight 0
-      float a = 0.0f;
-      Steps<0, 16>::run([&](auto kc) {
-        constexpr int K = decltype(kc)::value;
-        const float d0 = rshare<K>(xj[0]) - xi[0];
-        float s2 = d0 * d0;
-        if constexpr (DIM > 1) {
-          const float d1 = rshare<K>(xj[1]) - xi[1];
-          s2 = __builtin_fmaf(d1, d1, s2);
-        }
-        if constexpr (DIM > 2) {
-          const float d2 = rshare<K>(xj[2]) - xi[2];
-          s2 = __builtin_fmaf(d2, d2, s2);
-        }
-        const float w = kweight(s2, esc);
-        a += (act && s2 <= rc2) ? w : 0.0f;
-      });
-      acc += (double)a;
+      acc += (double)rowsum_chunk<DIM>(xj, xi, rc2, esc, act);
     });
   } else {
     acc = 1.0;
@@ -988,43 +945,9 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
       for (int s = 0; s < SMAX; ++s) accr[s] = 0.0f;
       float rr = 0.0f;
       if (sym) {
-        Steps<0, 16>::run([&](auto kc) {
-          constexpr int K = decltype(kc)::value;
-          const float d0 = rshare<K>(xj[0]) - xi[0];
-          float s2 = d0 * d0;
-          if constexpr (DIM > 1) {
-            const float d1 = rshare<K>(xj[1]) - xi[1];
-            s2 = __builtin_fmaf(d1, d1, s2);
-          }
-          if constexpr (DIM > 2) {
-            const float d2 = rshare<K>(xj[2]) - xi[2];
-            s2 = __builtin_fmaf(d2, d2, s2);
-          }
-          float w = kweight(s2, esc);
-          w = (act && s2 <= rc2) ? w : 0.0f;
-          const float p = w * (rshare<K>(qj) + qi);  // 2 * symmetric P_ij
-#pragma unroll
-          for (int s = 0; s < SMAX; ++s) accr[s] += p * (rshare<K>(mj[s]) - Mi[s]);
-        });
+        exchange_chunk_sym<DIM, SMAX>(xj, xi, qj, qi, mj, Mi, rc2, esc, act, accr);
       } else {
-        Steps<0, 16>::run([&](auto kc) {
-          constexpr int K = decltype(kc)::value;
-          const float d0 = rshare<K>(xj[0]) - xi[0];
-          float s2 = d0 * d0;
-          if constexpr (DIM > 1) {
-            const float d1 = rshare<K>(xj[1]) - xi[1];
-            s2 = __builtin_fmaf(d1, d1, s2);
-          }
-          if constexpr (DIM > 2) {
-            const float d2 = rshare<K>(xj[2]) - xi[2];
-            s2 = __builtin_fmaf(d2, d2, s2);
-          }
-          float w = kweight(s2, esc);
-          w = (act && s2 <= rc2) ? w : 0.0f;
-          rr += w;
-#pragma unroll
-          for (int s = 0; s < SMAX; ++s) accr[s] += w * (rshare<K>(mj[s]) - Mi[s]);
-        });
+        exchange_chunk_row<DIM, SMAX>(xj, xi, mj, Mi, rc2, esc, act, rr, accr);
       }
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];

@@ -20,6 +20,7 @@ RWPT_OK, RWPT_EINVAL, RWPT_ENOMEM, RWPT_EDEVICE, RWPT_ESTATE, RWPT_EUNSUPPORTED 
 RWPT_FP32, RWPT_FP64 = 0, 1
 RWPT_NORM_SYM, RWPT_NORM_ROW = 0, 1
 RWPT_PATH_AUTO, RWPT_PATH_SPARSE, RWPT_PATH_DENSE = 0, 1, 2
+RWPT_PROBE_FMA, RWPT_PROBE_EXP, RWPT_PROBE_ROWSUM, RWPT_PROBE_EXCHANGE = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "RWPT_OK", -1: "RWPT_EINVAL", -2: "RWPT_ENOMEM", -3: "RWPT_EDEVICE",
                 -4: "RWPT_ESTATE", -5: "RWPT_EUNSUPPORTED"}
@@ -30,8 +31,8 @@ EXPORTED = [
     "rwpt_step", "rwpt_sync", "rwpt_stats",
     "rwpt_query_masses", "rwpt_query_positions", "rwpt_audit", "rwpt_steps_taken",
     "rwpt_count_pairs", "rwpt_neighbors", "rwpt_profile_enable", "rwpt_profile_reset",
-    "rwpt_profile_read", "rwpt_profile_phase_name", "rwpt_get_tiling", "rwpt_autotune",
-    "rwpt_last_error", "rwpt_version", "rwpt_destroy",
+    "rwpt_profile_read", "rwpt_profile_phase_name", "rwpt_probe_rate", "rwpt_get_tiling",
+    "rwpt_autotune", "rwpt_last_error", "rwpt_version", "rwpt_destroy",
 ]
 
 
@@ -114,6 +115,7 @@ def load_library(path: str = LIB_PATH):
         "rwpt_profile_reset": (i32, [vp]),
         "rwpt_profile_read": (i32, [vp, vp, vp, ctypes.POINTER(i32)]),
         "rwpt_profile_phase_name": (ctypes.c_char_p, [i32]),
+        "rwpt_probe_rate": (i32, [vp, i32, ctypes.POINTER(f64)]),
         "rwpt_get_tiling": (i32, [vp, ctypes.POINTER(i32), vp]),
         "rwpt_autotune": (i32, [vp, f64, f64, i32]),
         "rwpt_last_error": (ctypes.c_char_p, [vp]),
@@ -256,6 +258,13 @@ def rwpt_profile_read(ctx) -> dict:
     return {lib.rwpt_profile_phase_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(n.value)}
 
 
+def rwpt_probe_rate(ctx, kind: int) -> float:
+    """Attainable rate of one probe kind (lane ops/s or candidate evaluations/s)."""
+    v = ctypes.c_double()
+    _check(load_library().rwpt_probe_rate(ctx, int(kind), ctypes.byref(v)), ctx)
+    return float(v.value)
+
+
 def rwpt_get_tiling(ctx):
     lanes = ctypes.c_int32()
     ref = np.zeros(3, dtype=np.float64)
@@ -345,6 +354,9 @@ class Ensemble:
 
     def stats(self):
         return rwpt_stats(self.ctx)
+
+    def probe_rate(self, kind):
+        return rwpt_probe_rate(self.ctx, kind)
 
     def neighbors(self, dt, D):
         return rwpt_neighbors(self.ctx, dt, D, self.n)

@@ -176,3 +176,25 @@ def test_device_init_validates_before_copy(lib):
         assert ei.value.status == rwpt.RWPT_EINVAL and "NULL" in str(ei.value)
     finally:
         rwpt.rwpt_destroy(ctx)
+
+
+def test_probe_rate_validates_before_device(lib):
+    ctx = rwpt.rwpt_create(rwpt.rwpt_config_default())
+    try:
+        for kind in (-1, 4):
+            with pytest.raises(rwpt.RwptError) as ei:
+                rwpt.rwpt_probe_rate(ctx, kind)
+            assert ei.value.status == rwpt.RWPT_EINVAL
+        assert lib.rwpt_probe_rate(ctx, rwpt.RWPT_PROBE_FMA, None) == rwpt.RWPT_EINVAL
+        assert lib.rwpt_probe_rate(None, rwpt.RWPT_PROBE_FMA, None) == rwpt.RWPT_EINVAL
+        try:
+            import torch
+            gpu = torch.cuda.is_available()
+        except Exception:
+            gpu = False
+        if not gpu:
+            with pytest.raises(rwpt.RwptError) as ei:
+                rwpt.rwpt_probe_rate(ctx, rwpt.RWPT_PROBE_ROWSUM)
+            assert ei.value.status == rwpt.RWPT_EDEVICE
+    finally:
+        rwpt.rwpt_destroy(ctx)
