@@ -822,13 +822,39 @@ __device__ __forceinline__ void cursor_advance(RowCursor& c, const RealParams& P
   }
 }
 
-// Calls chunk(j, has) for every chunk of 64 virtual candidates of every
-// segment of the tile; `act` marks the lanes whose particle is in the segment.
-template <typename ChunkFn>
+// Lane `lane` of the chunk starting at virtual index vbase: its candidate j
+// (or jdummy when the chunk runs past the segment's last row), advancing the
+// cursor over every row that ends inside the chunk.
+__device__ __forceinline__ void chunk_pick(RowCursor& c, const RealParams& P, const StencilRow* __restrict__ st,
+                                           const uint32_t* __restrict__ cell_start, int cy, int cz, int cxa,
+                                           int cxb, uint32_t vbase, int32_t jdummy, int32_t& j, bool& has) {
+  const uint32_t v = vbase + (uint32_t)(threadIdx.x & 63);
+  j = jdummy;
+  has = false;
+  while (c.valid) {
+    const uint32_t len = c.je - c.jb;
+    if (v >= c.p && v < c.p + len) {
+      j = (int32_t)(c.jb + (v - c.p));
+      has = true;
+    }
+    if (c.p + len <= vbase + 64) {
+      c.p += len;
+      cursor_advance(c, P, st, cell_start, cy, cz, cxa, cxb);
+    } else {
+      break;
+    }
+  }
+}
+
+// Runs compute(load(j, has), act) for every chunk of 64 virtual candidates of
+// every segment of the tile; `act` marks the lanes whose particle is in the
+// segment.  Software-pipelined: the candidates of the next chunk are picked
+// and their loads issued before the current chunk is computed, so the load
+// latency overlaps the chunk's arithmetic.
+template <typename LoadFn, typename ComputeFn>
 __device__ __forceinline__ void for_tile_chunks(const RealParams& P, const StencilRow* __restrict__ st,
                                                 const uint32_t* __restrict__ cell_start, const TileLane& tl,
-                                                int32_t jdummy, ChunkFn&& chunk) {
-  const int lane = threadIdx.x & 63;
+                                                int32_t jdummy, LoadFn&& load, ComputeFn&& compute) {
   const int nc1 = P.nc[1];
   int seg = 0;
   while (seg < tl.n_in) {
@@ -845,28 +871,24 @@ __device__ __forceinline__ void for_tile_chunks(const RealParams& P, const Stenc
     c.r = 0;
     c.p = 0;
     cursor_advance(c, P, st, cell_start, cy, cz, cxa, cxb);
-    uint32_t vbase = 0;
-    bool more = c.valid;
-    while (more) {
-      const uint32_t v = vbase + (uint32_t)lane;
-      int32_t j = jdummy;
-      bool has = false;
-      while (c.valid) {
-        const uint32_t len = c.je - c.jb;
-        if (v >= c.p && v < c.p + len) {
-          j = (int32_t)(c.jb + (v - c.p));
-          has = true;
+    if (c.valid) {
+      uint32_t vbase = 0;
+      int32_t j;
+      bool has;
+      chunk_pick(c, P, st, cell_start, cy, cz, cxa, cxb, vbase, jdummy, j, has);
+      auto cur = load(j, has);
+      while (true) {
+        const bool next = c.valid;
+        decltype(cur) nxt = cur;
+        if (next) {
+          vbase += 64;
+          chunk_pick(c, P, st, cell_start, cy, cz, cxa, cxb, vbase, jdummy, j, has);
+          nxt = load(j, has);
         }
-        if (c.p + len <= vbase + 64) {
-          c.p += len;
-          cursor_advance(c, P, st, cell_start, cy, cz, cxa, cxb);
-        } else {
-          break;
-        }
+        compute(cur, act);
+        if (!next) break;
+        cur = nxt;
       }
-      chunk(j, has, act);
-      more = c.valid;
-      vbase += 64;
     }
     seg = seg_end;
   }
@@ -889,12 +911,25 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
   const float rc2 = P.rc2_f, esc = P.escale_f;
   double acc = 0.0;
   if (P.active) {
-    for_tile_chunks(P, st, cell_start, tl, tile.begin, [&](int32_t j, bool has, bool act) {
-      float xj[DIM];
-      load_pos<float, DIM>(pos, j, xj);
-      if (!has) xj[0] = 3.0e38f;  // s^2 overflows to +inf: outside the cutoff, weight 0
-      acc += (double)rowsum_chunk<DIM>(xj, xi, rc2, esc, act);
-    });
+    struct Cand {
+      float x[DIM];
+      bool has;
+    };
+    for_tile_chunks(
+        P, st, cell_start, tl, tile.begin,
+        [&](int32_t j, bool has) {
+          Cand d;
+          load_pos<float, DIM>(pos, j, d.x);
+          d.has = has;
+          return d;
+        },
+        [&](const Cand& d, bool act) {
+          float xj[DIM];
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) xj[k] = d.x[k];
+          if (!d.has) xj[0] = 3.0e38f;  // s^2 overflows to +inf: outside the cutoff, weight 0
+          acc += (double)rowsum_chunk<DIM>(xj, xi, rc2, esc, act);
+        });
   } else {
     acc = 1.0;
   }
@@ -933,26 +968,41 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
   const bool sym = (norm == 0);
   const float qi = q[ii];
   if (P.active) {
-    for_tile_chunks(P, st, cell_start, tl, tile.begin, [&](int32_t j, bool has, bool act) {
-      float xj[DIM], mj[SMAX];
-      load_pos<float, DIM>(pos, j, xj);
-      if (!has) xj[0] = 3.0e38f;  // outside the cutoff, weight 0
-      const float qj = q[j];
-      // species slots S..SMAX-1 exist and hold zeros, so no guard is needed
-      load_mass<float, SMAX>(min_, j, mj);
-      float accr[SMAX];
+    struct Cand {
+      float x[DIM], m[SMAX], q;
+      bool has;
+    };
+    for_tile_chunks(
+        P, st, cell_start, tl, tile.begin,
+        [&](int32_t j, bool has) {
+          Cand d;
+          load_pos<float, DIM>(pos, j, d.x);
+          d.q = q[j];
+          // species slots S..SMAX-1 exist and hold zeros, so no guard is needed
+          load_mass<float, SMAX>(min_, j, d.m);
+          d.has = has;
+          return d;
+        },
+        [&](const Cand& d, bool act) {
+          float xj[DIM], mj[SMAX];
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) accr[s] = 0.0f;
-      float rr = 0.0f;
-      if (sym) {
-        exchange_chunk_sym<DIM, SMAX>(xj, xi, qj, qi, mj, Mi, rc2, esc, act, accr);
-      } else {
-        exchange_chunk_row<DIM, SMAX>(xj, xi, mj, Mi, rc2, esc, act, rr, accr);
-      }
+          for (int k = 0; k < DIM; ++k) xj[k] = d.x[k];
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
-      racc += (double)rr;
-    });
+          for (int s = 0; s < SMAX; ++s) mj[s] = d.m[s];
+          if (!d.has) xj[0] = 3.0e38f;  // outside the cutoff, weight 0
+          float accr[SMAX];
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s) accr[s] = 0.0f;
+          float rr = 0.0f;
+          if (sym) {
+            exchange_chunk_sym<DIM, SMAX>(xj, xi, d.q, qi, mj, Mi, rc2, esc, act, accr);
+          } else {
+            exchange_chunk_row<DIM, SMAX>(xj, xi, mj, Mi, rc2, esc, act, rr, accr);
+          }
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
+          racc += (double)rr;
+        });
   }
 #pragma unroll
   for (int off = 16; off < 64; off <<= 1) {
@@ -1273,6 +1323,54 @@ __global__ __launch_bounds__(kBlock) void k_count(PairArgs a) {
       for (uint32_t c = 0; c < nfull; ++c, j += L) body(j);
       if (rem && (uint32_t)tl.gl < rem) body(j);
     });
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    pairs += __shfl_xor(pairs, off);
+    evals += __shfl_xor(evals, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    const int t = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    a.counts[2 * t] = pairs;
+    a.counts[2 * t + 1] = evals;
+  }
+}
+
+// The same counts for the private-list kernels: every particle's candidates
+// are the cells of its own cutoff box, enumerated as k_rowsum_priv does.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_count_priv(PairArgs a) {
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<0>(a.tiles, a.ntiles, tl, tile)) return;
+  const RealParams& P = a.rp[tile.real];
+  const T* __restrict__ pos = (const T*)a.pos;
+  const int32_t ii = tl.valid ? tl.i : tile.end - 1;
+  T xi[DIM];
+  load_pos<T, DIM>(pos, ii, xi);
+  const T rc2 = rc2_of<T>(P);
+  unsigned long long pairs = 0, evals = 0;
+  if (P.active && tl.valid) {
+    const double rg = P.rc_geo;
+    int ca[3] = {0, 0, 0}, cb_[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      ca[k] = cell_of(P, k, (double)xi[k] - rg);
+      cb_[k] = cell_of(P, k, (double)xi[k] + rg);
+    }
+    const uint32_t nc0 = (uint32_t)P.nc[0], nc1 = (uint32_t)P.nc[1];
+    const uint32_t coff = (uint32_t)P.cell_off;
+    for (int zz = ca[2]; zz <= cb_[2]; ++zz) {
+      for (int yy = ca[1]; yy <= cb_[1]; ++yy) {
+        const uint32_t base = coff + ((uint32_t)zz * nc1 + (uint32_t)yy) * nc0;
+        const uint32_t jb = a.cell_start[base + (uint32_t)ca[0]];
+        const uint32_t je = a.cell_start[base + (uint32_t)cb_[0] + 1u];
+        for (uint32_t j = jb; j < je; ++j) {
+          ++evals;
+          if (sep2<T, DIM>(xi, pos, j) <= rc2 && j != (uint32_t)ii) ++pairs;
+        }
+      }
+    }
   }
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -1634,8 +1732,12 @@ hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipS
 
 hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
-  if (log2l == kPrivateLists) log2l = 0;  // same tiles of 64
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
+  if (log2l == kPrivateLists) {  // same tiles of 64, one lane per particle
+    return dispatch_tdl(fp64, dim, 0, [&](auto t, auto d, auto) {
+      hipLaunchKernelGGL((k_count_priv<decltype(t), decltype(d)::value>), g, b, 0, s, a);
+    });
+  }
   return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
     using T = decltype(t);
     hipLaunchKernelGGL((k_count<T, decltype(d)::value, decltype(l)::value>), g, b, 0, s, a);

@@ -254,6 +254,13 @@ def test_walk3d_eight_species(prec, tol, lanes):
     rp, cols = ens.neighbors(dt, D)
     rp0, cols0 = oracle.neighbors(pos, 3.0, D, dt, 32 if prec == F32 else 64)
     assert np.array_equal(rp, rp0) and np.array_equal(cols, cols0)
+    pairs, evals = ens.count_pairs(dt, D)
+    assert pairs == rp0[-1] - n and evals >= rp0[-1]
+    if ens.stats()["tile_lanes"] == -1:
+        # one lane per particle: only the cells of its own cutoff box (about
+        # 2 x 2 x 2 cells of two cutoffs, ~16 candidates here for ~2 neighbours
+        # including itself), not the candidate union of a 64-particle tile
+        assert evals < 16 * rp0[-1]
     ens.close()
 
 
