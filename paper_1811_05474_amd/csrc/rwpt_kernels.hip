@@ -596,6 +596,8 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(
     T* __restrict__ q_out) {
   constexpr int L = 1 << LOG2L;
   constexpr int G = 64 >> LOG2L;
+  WeightFn<T> wfn;  // before any return: the binary64 form has a block barrier
+  wfn.setup();
   TileLane tl;
   Tile tile;
   if (!tile_lane_setup<LOG2L>(tiles, ntiles, tl, tile)) return;
@@ -622,7 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
             const T s2 = sep2v<T, DIM>(xi, xj[u]);
-            const T w = kweight(s2, esc);
+            const T w = wfn(s2, esc);
             accr += (act && s2 <= rc2) ? w : (T)0;
           }
         }
@@ -631,7 +633,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(
       }
       for (; j < je; j += L) {
         const T s2 = sep2<T, DIM>(xi, pos, j);
-        const T w = kweight(s2, esc);
+        const T w = wfn(s2, esc);
         accr += (act && s2 <= rc2) ? w : (T)0;
       }
       acc += (double)accr;
@@ -660,6 +662,8 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
     const int32_t norm, double* __restrict__ audit_part) {
   constexpr int L = 1 << LOG2L;
   constexpr int G = 64 >> LOG2L;
+  WeightFn<T> wfn;  // before any return: the binary64 form has a block barrier
+  wfn.setup();
   TileLane tl;
   Tile tile;
   if (!tile_lane_setup<LOG2L>(tiles, ntiles, tl, tile)) return;
@@ -688,7 +692,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
         // species slots S..SMAX-1 exist and hold zeros, so no guard is needed
         auto eval = [&](const T xj[DIM], T qj, const T mj[SMAX]) {
           const T s2 = sep2v<T, DIM>(xi, xj);
-          T w = kweight(s2, esc);
+          T w = wfn(s2, esc);
           w = (act && s2 <= rc2) ? w : (T)0;
           const T p = w * (qi + qj);  // 2 * symmetric P_ij
 #pragma unroll
@@ -732,7 +736,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
         uint32_t j = jb + tl.gl;
         auto eval = [&](const T xj[DIM], const T mj[SMAX]) {
           const T s2 = sep2v<T, DIM>(xi, xj);
-          T w = kweight(s2, esc);
+          T w = wfn(s2, esc);
           w = (act && s2 <= rc2) ? w : (T)0;
           rr += w;
 #pragma unroll
@@ -1079,6 +1083,8 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_priv(
     T* __restrict__ q_out, uint16_t* __restrict__ nb_meta, uint32_t* __restrict__ nb_idx,
     T* __restrict__ nb_w, uint32_t* __restrict__ nb_src, const uint32_t* __restrict__ src_of) {
   constexpr int RB = PrivBatch<DIM>::kRowBatch, CB = PrivBatch<DIM>::kCandBatch;
+  WeightFn<T> wfn;  // before any return: the binary64 form has a block barrier
+  wfn.setup();
   TileLane tl;
   Tile tile;
   if (!tile_lane_setup<0>(tiles, ntiles, tl, tile)) return;
@@ -1145,7 +1151,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_priv(
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
           const T s2 = sep2v<T, DIM>(xi, xj[u]);
-          const T w = kweight(s2, esc);
+          const T w = wfn(s2, esc);
           const bool hit = t0 + u < total && s2 <= rc2;
           a += hit ? w : (T)0;
           if (hit && jv[u] != (uint32_t)ii && cnt <= (uint32_t)kCacheLane) {
@@ -1209,6 +1215,8 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
     const int32_t react_a, const int32_t react_b, const int32_t norm, double* __restrict__ audit_part,
     const uint16_t* __restrict__ nb_meta, const uint32_t* __restrict__ nb_idx, const T* __restrict__ nb_w,
     const uint32_t* __restrict__ nb_src, const uint32_t* __restrict__ src_of) {
+  WeightFn<T> wfn;  // before any return: the binary64 form has a block barrier
+  wfn.setup();
   TileLane tl;
   Tile tile;
   if (!tile_lane_setup<0>(tiles, ntiles, tl, tile)) return;
@@ -1273,7 +1281,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
         for (uint32_t j = jb; j < je; ++j) {
           const T s2 = sep2<T, DIM>(xi, pos, j);
           if (!(s2 <= rc2)) continue;  // sparse: most candidates miss, skip their loads
-          const T w = kweight(s2, esc);
+          const T w = wfn(s2, esc);
           // species slots S..SMAX-1 exist and hold zeros
           const T p = sym ? w * (qi + q[j]) : w;
           rr += w;
