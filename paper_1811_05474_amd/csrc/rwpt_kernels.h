@@ -21,6 +21,7 @@ enum Phase {
 constexpr int kBlock = 256;        // threads per block of every kernel
 constexpr int kScanItems = 16;     // counts per thread in the cell-count scan
 constexpr int kScanChunk = kBlock * kScanItems;
+constexpr int64_t kScanDirectMax = 256;  // up to this many scan blocks (one partial per thread), no top-level scan launch
 
 // Random walk + reflection (optional) and cell key / in-cell slot of every particle.
 // pos_in/pos_out may not alias.

@@ -288,7 +288,11 @@ __device__ __forceinline__ int scan_pad(int k) { return k + (k >> 4); }
 // Final pass: coalesced striped loads into LDS, a sequential scan of 16
 // consecutive elements per thread, a block scan of the thread sums, then
 // coalesced striped stores of the cell starts; the counts are re-zeroed for
-// the next step.
+// the next step.  DIRECT: partials holds the block sums themselves and every
+// block adds up those of the blocks before it (no top-level scan launch; the
+// last block writes the grand total start[n]); otherwise partials holds their
+// exclusive scan.
+template <bool DIRECT>
 __global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t* __restrict__ cnt, int64_t n,
                                                        const uint32_t* __restrict__ partials,
                                                        uint32_t* __restrict__ start) {
@@ -296,6 +300,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t* __restrict__ cn
   __shared__ uint32_t buf[kScanChunk + kScanChunk / 16];
   const int t = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint32_t prefix = 0;
+  if constexpr (DIRECT) {
+    uint32_t s = 0;
+    for (int c = t; c < (int)blockIdx.x; c += kBlock) s += partials[c];
+    block_inclusive_scan(s, sh, &prefix);
+  } else {
+    prefix = partials[blockIdx.x];
+  }
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     const int k = t + i * kBlock;
@@ -311,7 +323,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t* __restrict__ cn
   }
   uint32_t total;
   const uint32_t incl = block_inclusive_scan(sum, sh, &total);
-  uint32_t run = partials[blockIdx.x] + incl - sum;
+  if constexpr (DIRECT) {
+    if (t == 0 && blockIdx.x == gridDim.x - 1) start[n] = prefix + total;
+  }
+  uint32_t run = prefix + incl - sum;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     buf[scan_pad(t * kScanItems + i)] = run;
@@ -1565,9 +1580,15 @@ hipError_t launch_cell_scan(uint32_t* cell_count, uint32_t* cell_start, int64_t 
                             uint32_t* partials, hipStream_t s) {
   const int64_t nb = (ncell + kScanChunk - 1) / kScanChunk;
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, cell_count, ncell, partials);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, partials, (int32_t)nb, cell_start, ncell);
-  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, cell_count, ncell, partials,
-                     cell_start);
+  if (nb <= kScanDirectMax) {
+    // each block sums the block partials before it, at most one per thread
+    hipLaunchKernelGGL(k_scan_final<true>, dim3((unsigned)nb), dim3(kBlock), 0, s, cell_count, ncell, partials,
+                       cell_start);
+  } else {
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, partials, (int32_t)nb, cell_start, ncell);
+    hipLaunchKernelGGL(k_scan_final<false>, dim3((unsigned)nb), dim3(kBlock), 0, s, cell_count, ncell, partials,
+                       cell_start);
+  }
   return hipGetLastError();
 }
 

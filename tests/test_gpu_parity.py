@@ -789,3 +789,24 @@ def test_graph_eager_split_and_interleaved_queries_agree_bitwise(lanes, rw, prec
         ref = oracle_run(f32(x) if prec == F32 else x, f32(M) if prec == F32 else M, D, dt, 7, 3.0,
                          32 if prec == F32 else 64)
         assert normerr(runs[0][0], ref) < (1e-5 if prec == F32 else 1e-12)
+
+
+def test_cell_scan_both_forms_agree():
+    """Grids of more than 256 scan blocks (1.05e6 cells) take the three-launch
+    cell scan, smaller ones the two-launch form: the same FP64 step on both
+    grids gives the same masses (same neighbour sets, summation order aside)."""
+    n, D, dt = 5_000_000, 1e-6, 0.1
+    x = W.positions(n, 2, 77)
+    M = W.masses(n, 2, 77)
+    out = []
+    for refine in ((32.0, 32.0, 0.0), (2.0, 2.0, 0.0)):
+        ens = make(dim=2, prec=F64, refine=refine, seed=77)
+        ens.init([n], x, M)
+        ens.step(dt, D, 1)
+        st = ens.stats()
+        out.append((st["n_cells"], ens.masses(), ens.count_pairs(dt, D)[0]))
+        ens.close()
+    (cells_big, m_big, p_big), (cells_small, m_small, p_small) = out
+    assert cells_big > 256 * 4096 >= cells_small
+    assert p_big == p_small
+    assert normerr(m_big, m_small) < 1e-12
