@@ -177,6 +177,36 @@ def test_walk2d_n1e6_one_step_sampled():
     ens.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(F32, 1e-5), (F64, 1e-12)])
+def test_walk3d_n8e6_one_step_sampled(prec, tol):
+    """The 3-D, eight-species workload at full size (8e6 particles) in the
+    tiling the benchmark times (one lane per particle): one step, sampled
+    particles against the oracle, and the pair count against the closed form."""
+    w = W.WORKLOADS["walk3d_n8e6_s8"]
+    x, M, sizes, _ = W.make_inputs(w)
+    if prec == F32:
+        x, M = f32(x), f32(M)
+    ens = make(dim=3, S=8, rw=1.0, prec=prec, seed=w.seed)
+    ens.init(sizes, x, M)
+    ens.step(w.dt, w.D, 1)
+    assert ens.stats()["tile_lanes"] == -1
+    pos = ens.positions()
+    got = ens.masses()
+    rows = np.random.default_rng(6).choice(w.n, 4000, replace=False)
+    walked = oracle.walk(x[rows], rows.astype(np.uint32), w.seed, 0, w.D, w.dt, (0, 0, 0), (1, 1, 1))
+    assert np.abs(pos[rows] - walked).max() < (2e-6 if prec == F32 else 1e-12)
+    ref = oracle.transfer(pos, M, w.D, w.dt, kappa=3.0, prec=32 if prec == F32 else 64, rows=rows)
+    assert normerr(got[:, rows], ref) < tol
+    # ordered pairs: n (n - 1) F(r) with the unit-cube pair-distance CDF
+    # F(r) = 4 pi r^3 / 3 - 3 pi r^4 / 2 + 8 r^5 / 5 - r^6 / 6 (r <= 1)
+    pairs, _ = ens.count_pairs(w.dt, w.D)
+    r = 3 * math.sqrt(8 * w.D * w.dt)
+    F = 4 * math.pi * r ** 3 / 3 - 1.5 * math.pi * r ** 4 + 1.6 * r ** 5 - r ** 6 / 6
+    expect = w.n * (w.n - 1) * F
+    assert abs(pairs - expect) < 6 * math.sqrt(4 * expect)
+    ens.close()
+
+
 def test_walk2d_n1e6_conservation_over_steps():
     w = W.WORKLOADS["walk2d_n1e6"]
     x, M, sizes, _ = W.make_inputs(w)
