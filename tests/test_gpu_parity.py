@@ -245,6 +245,31 @@ def test_batched_realisations_match_independent_oracles():
     ens.close()
 
 
+def test_batch2d_64_full_size_sampled():
+    """All 64 realisations (4.24e6 particles, D alternating 1e-5 / 1e-4) with
+    the walk, in the launch configuration the benchmark times: sampled
+    particles of six realisations against the oracle's walk and transfer."""
+    w = W.WORKLOADS["batch2d_64"]
+    x, M, sizes, Ds = W.make_inputs(w)
+    x, M = f32(x), f32(M)
+    ens = make(dim=2, rw=1.0, prec=F32, seed=w.seed)
+    ens.init(sizes, x, M, d_scale=Ds / w.D)
+    ens.step(w.dt, w.D, 1)
+    pos = ens.positions()
+    got = ens.masses()
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    order = np.argsort(sizes)
+    rng = np.random.default_rng(8)
+    for r in [int(order[0]), int(order[1]), int(order[-1]), int(order[-2]), 10, 11]:
+        b, e = int(off[r]), int(off[r + 1])
+        rows = rng.choice(e - b, min(400, e - b), replace=False)
+        walked = oracle.walk(x[b + rows], (b + rows).astype(np.uint32), w.seed, 0, Ds[r], w.dt, (0, 0), (1, 1))
+        assert np.abs(pos[b + rows] - walked).max() < 2e-6, r
+        ref = oracle.transfer(pos[b:e], M[:, b:e], Ds[r], w.dt, kappa=3.0, prec=32, rows=rows)
+        assert normerr(got[:, b + rows], ref) < 1e-5, r
+    ens.close()
+
+
 def test_batch_with_empty_and_single_realisations():
     sizes = [0, 1, 37, 0, 130, 1]
     n = sum(sizes)
