@@ -33,6 +33,15 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x * per + (x < rem ? x : rem) + q;
 }
 
+// Tile index of the calling wave, as tile_lane_setup derives it (SPLIT > 1:
+// one tile per block).
+template <int SPLIT = 1>
+__device__ __forceinline__ int64_t wave_tile() {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  return SPLIT > 1 ? blk : blk * (kBlock / 64) + wave;
+}
+
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): 10 rounds of the
 // multiply/xor S-box with the key bumped by the golden-ratio and sqrt(3)-1
 // Weyl constants between rounds.
@@ -446,9 +455,12 @@ __device__ __forceinline__ void for_tile_rows(const RealParams& P, const Stencil
 }
 
 // Load the tile header and this lane's particle.
-template <int LOG2L>
+// SPLIT > 1: the SPLIT = kBlock / 64 waves of a block share one tile (each
+// takes every SPLIT-th chunk of its candidates); otherwise one tile per wave.
+template <int LOG2L, int SPLIT = 1>
 __device__ __forceinline__ bool tile_lane_setup(const Tile* __restrict__ tiles, int32_t ntiles,
                                                 TileLane& tl, Tile& tile) {
+  static_assert(SPLIT == 1 || SPLIT == kBlock / 64, "a split tile takes the waves of one block");
   constexpr int G = 64 >> LOG2L;
   const int lane = threadIdx.x & 63;
   // the wave index is uniform across the wave; say so, so that everything
@@ -456,7 +468,7 @@ __device__ __forceinline__ bool tile_lane_setup(const Tile* __restrict__ tiles, 
   // scalar cache
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int t = blk * (kBlock / 64) + wave;
+  const int t = SPLIT > 1 ? blk : blk * (kBlock / 64) + wave;
   if (t >= ntiles) return false;
   tile = tiles[t];
   tl.gi = lane & (G - 1);
@@ -543,7 +555,7 @@ template <typename T, int SMAX, int G>
 __device__ __forceinline__ void exchange_epilogue(const RealParams& P, bool sym, const double acc[SMAX],
                                                   double racc, const T Mi[SMAX], bool writer, int32_t i,
                                                   T* __restrict__ mout, int S, int react_a,
-                                                  int react_b, double* __restrict__ audit_part) {
+                                                  int react_b, double* __restrict__ audit_part, int64_t t) {
   double tot[SMAX + 1];
 #pragma unroll
   for (int s = 0; s <= SMAX; ++s) tot[s] = 0.0;
@@ -588,8 +600,7 @@ __device__ __forceinline__ void exchange_epilogue(const RealParams& P, bool sym,
   int idx = 0, real = NV;
   halve_sum<1, G, NV, NV>(tot, idx, real, lane);
   if (lane < (1 << NB)) {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
-    double* part = audit_part + (int64_t)t * (S + 1);
+    double* part = audit_part + t * (S + 1);
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
       const int vi = idx + k;
@@ -796,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange(
     racc += __shfl_xor(racc, off);
   }
   exchange_epilogue<T, SMAX, G>(P, sym, acc, racc, Mi, tl.gl == 0 && tl.valid, tl.i, mout, S, react_a,
-                                react_b, audit_part);
+                                react_b, audit_part, wave_tile());
 }
 
 // ---------------------------------------------------------------------------
@@ -866,14 +877,15 @@ __device__ __forceinline__ void chunk_pick(RowCursor& c, const RealParams& P, co
 }
 
 // Runs compute(load(j, has), act) for every chunk of 64 virtual candidates of
-// every segment of the tile; `act` marks the lanes whose particle is in the
-// segment.  Software-pipelined: the candidates of the next chunk are picked
-// and their loads issued before the current chunk is computed, so the load
-// latency overlaps the chunk's arithmetic.
-template <typename LoadFn, typename ComputeFn>
+// every segment of the tile (NPARTS > 1: only chunks part, part + NPARTS, ...;
+// the cursor still walks the others, without loads); `act` marks the lanes
+// whose particle is in the segment.  Software-pipelined: the candidates of the
+// next chunk are picked and their loads issued before the current chunk is
+// computed, so the load latency overlaps the chunk's arithmetic.
+template <int NPARTS, typename LoadFn, typename ComputeFn>
 __device__ __forceinline__ void for_tile_chunks(const RealParams& P, const StencilRow* __restrict__ st,
                                                 const uint32_t* __restrict__ cell_start, const TileLane& tl,
-                                                int32_t jdummy, LoadFn&& load, ComputeFn&& compute) {
+                                                int32_t jdummy, int part, LoadFn&& load, ComputeFn&& compute) {
   const int nc1 = P.nc[1];
   int seg = 0;
   while (seg < tl.n_in) {
@@ -890,13 +902,26 @@ __device__ __forceinline__ void for_tile_chunks(const RealParams& P, const Stenc
     c.r = 0;
     c.p = 0;
     cursor_advance(c, P, st, cell_start, cy, cz, cxa, cxb);
+    // after picking the chunk at vbase, c.valid says whether a chunk follows
+    uint32_t vbase = 0;
+    int32_t j;
+    bool has;
+    if constexpr (NPARTS > 1) {
+      for (int k = 0; k < part && c.valid; ++k) {  // chunks before this part's first
+        chunk_pick(c, P, st, cell_start, cy, cz, cxa, cxb, vbase, jdummy, j, has);
+        vbase += 64;
+      }
+    }
     if (c.valid) {
-      uint32_t vbase = 0;
-      int32_t j;
-      bool has;
       chunk_pick(c, P, st, cell_start, cy, cz, cxa, cxb, vbase, jdummy, j, has);
       auto cur = load(j, has);
       while (true) {
+        if constexpr (NPARTS > 1) {
+          for (int k = 1; k < NPARTS && c.valid; ++k) {  // the other parts' chunks
+            vbase += 64;
+            chunk_pick(c, P, st, cell_start, cy, cz, cxa, cxb, vbase, jdummy, j, has);
+          }
+        }
         const bool next = c.valid;
         decltype(cur) nxt = cur;
         if (next) {
@@ -913,7 +938,7 @@ __device__ __forceinline__ void for_tile_chunks(const RealParams& P, const Stenc
   }
 }
 
-template <int DIM>
+template <int DIM, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
     const float* __restrict__ pos, const uint32_t* __restrict__ skey,
     const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles, const int32_t ntiles,
@@ -921,7 +946,8 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
     float* __restrict__ q_out) {
   TileLane tl;
   Tile tile;
-  if (!tile_lane_setup<2>(tiles, ntiles, tl, tile)) return;
+  if (!tile_lane_setup<2, SPLIT>(tiles, ntiles, tl, tile)) return;  // block-uniform when SPLIT > 1
+  const int part = SPLIT > 1 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
   const RealParams& P = rp[tile.real];
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   float xi[DIM];
@@ -934,8 +960,8 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
       float x[DIM];
       bool has;
     };
-    for_tile_chunks(
-        P, st, cell_start, tl, tile.begin,
+    for_tile_chunks<SPLIT>(
+        P, st, cell_start, tl, tile.begin, part,
         [&](int32_t j, bool has) {
           Cand d;
           load_pos<float, DIM>(pos, j, d.x);
@@ -952,6 +978,16 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
   } else {
     acc = 1.0;
   }
+  if constexpr (SPLIT > 1) {
+    // the parts' partial sums, added in part order by the first wave
+    __shared__ double sh_part[SPLIT - 1][64];
+    const int lane = threadIdx.x & 63;
+    if (part > 0) sh_part[part - 1][lane] = acc;
+    __syncthreads();
+    if (part > 0) return;
+#pragma unroll
+    for (int w = 0; w < SPLIT - 1; ++w) acc += sh_part[w][lane];
+  }
   acc += __shfl_xor(acc, 16);
   acc += __shfl_xor(acc, 32);
   if (tl.gl == 0 && tl.valid) {
@@ -961,7 +997,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
   }
 }
 
-template <int DIM, int SMAX>
+template <int DIM, int SMAX, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
     const float* __restrict__ pos, const float* __restrict__ min_, float* __restrict__ mout,
     const float* __restrict__ q, const uint32_t* __restrict__ skey, const uint32_t* __restrict__ cell_start,
@@ -971,7 +1007,8 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
   constexpr int G = 16;
   TileLane tl;
   Tile tile;
-  if (!tile_lane_setup<2>(tiles, ntiles, tl, tile)) return;
+  if (!tile_lane_setup<2, SPLIT>(tiles, ntiles, tl, tile)) return;  // block-uniform when SPLIT > 1
+  const int part = SPLIT > 1 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
   const RealParams& P = rp[tile.real];
   const int32_t ii = tl.valid ? tl.i : tile.end - 1;
   float xi[DIM];
@@ -991,8 +1028,8 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
       float x[DIM], m[SMAX], q;
       bool has;
     };
-    for_tile_chunks(
-        P, st, cell_start, tl, tile.begin,
+    for_tile_chunks<SPLIT>(
+        P, st, cell_start, tl, tile.begin, part,
         [&](int32_t j, bool has) {
           Cand d;
           load_pos<float, DIM>(pos, j, d.x);
@@ -1023,6 +1060,24 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
           racc += (double)rr;
         });
   }
+  if constexpr (SPLIT > 1) {
+    // the parts' partial sums, added in part order by the first wave
+    __shared__ double sh_part[SPLIT - 1][SMAX + 1][64];
+    const int lane = threadIdx.x & 63;
+    if (part > 0) {
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) sh_part[part - 1][s][lane] = acc[s];
+      sh_part[part - 1][SMAX][lane] = racc;
+    }
+    __syncthreads();
+    if (part > 0) return;
+#pragma unroll
+    for (int w = 0; w < SPLIT - 1; ++w) {
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) acc[s] += sh_part[w][s][lane];
+      racc += sh_part[w][SMAX][lane];
+    }
+  }
 #pragma unroll
   for (int off = 16; off < 64; off <<= 1) {
 #pragma unroll
@@ -1030,7 +1085,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
     racc += __shfl_xor(racc, off);
   }
   exchange_epilogue<float, SMAX, G>(P, sym, acc, racc, Mi, tl.gl == 0 && tl.valid, tl.i, mout, S,
-                                    react_a, react_b, audit_part);
+                                    react_a, react_b, audit_part, wave_tile<SPLIT>());
 }
 
 // ---------------------------------------------------------------------------
@@ -1060,11 +1115,6 @@ __device__ __forceinline__ void for_own_rows(const RealParams& P, const StencilR
   }
 }
 
-// Tile (wave) index of the calling wave, as tile_lane_setup derives it.
-__device__ __forceinline__ int64_t wave_tile() {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  return (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + wave;
-}
 
 // Row-sum pass of the one-lane-per-particle kernels.  Each lane takes the
 // cells its own cutoff box [x - r, x + r]^d overlaps (r the geometric cutoff,
@@ -1312,7 +1362,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
     }
   }
   exchange_epilogue<T, SMAX, 64>(P, sym, acc, racc, Mi, tl.valid, tl.i, mout, S, react_a, react_b,
-                                 audit_part);
+                                 audit_part, wave_tile());
 }
 
 // Counts ordered pairs j != i within the cutoff and candidate evaluations.
@@ -1639,6 +1689,11 @@ hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
   return hipGetLastError();
 }
 
+// Up to this many tiles, the row-broadcast kernels give each tile a whole
+// block (its four waves take every fourth chunk of the candidates), so that a
+// small ensemble still puts enough waves on the 1024 SIMDs to hide latency.
+constexpr int32_t kSplitTiles = 4096;
+
 static inline dim3 pair_grid(int32_t ntiles) {
   return dim3((unsigned)((ntiles + (kBlock / 64) - 1) / (kBlock / 64)));
 }
@@ -1686,9 +1741,15 @@ hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStr
     });
   }
   if (!fp64 && log2l == 2) {
+    const bool split = a.ntiles <= kSplitTiles;
+    const dim3 gs = split ? dim3((unsigned)a.ntiles) : g;
     auto go = [&](auto d) {
-      hipLaunchKernelGGL((k_rowsum_dpp<decltype(d)::value>), g, b, 0, s, (const float*)a.pos, a.skey,
-                         a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (float*)a.q_out);
+      constexpr int D = decltype(d)::value;
+#define RWPT_RSD_ARGS \
+  (const float*)a.pos, a.skey, a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.r_out, (float*)a.q_out
+      if (split) hipLaunchKernelGGL((k_rowsum_dpp<D, kBlock / 64>), gs, b, 0, s, RWPT_RSD_ARGS);
+      else hipLaunchKernelGGL((k_rowsum_dpp<D, 1>), gs, b, 0, s, RWPT_RSD_ARGS);
+#undef RWPT_RSD_ARGS
     };
     if (dim == 1) go(IC<1>{});
     else if (dim == 2) go(IC<2>{});
@@ -1730,14 +1791,21 @@ hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipS
     });
   }
   if (!fp64 && log2l == 2) {
+    const bool split = a.ntiles <= kSplitTiles;
+    const dim3 gs = split ? dim3((unsigned)a.ntiles) : g;
     auto go = [&](auto d) {
       constexpr int D = decltype(d)::value;
 #define RWPT_EXD_ARGS                                                                                  \
   (const float*)a.pos, (const float*)a.mass_in, (float*)a.mass_out, (const float*)a.q_in, a.skey, \
       a.cell_start, a.tiles, a.ntiles, a.rp, a.st, a.S, a.react_a, a.react_b, a.norm, a.audit_part
-      if (a.S <= 2) hipLaunchKernelGGL((k_exchange_dpp<D, 2>), g, b, 0, s, RWPT_EXD_ARGS);
-      else if (a.S <= 4) hipLaunchKernelGGL((k_exchange_dpp<D, 4>), g, b, 0, s, RWPT_EXD_ARGS);
-      else hipLaunchKernelGGL((k_exchange_dpp<D, 8>), g, b, 0, s, RWPT_EXD_ARGS);
+      auto go_s = [&](auto sm) {
+        constexpr int SM = decltype(sm)::value;
+        if (split) hipLaunchKernelGGL((k_exchange_dpp<D, SM, kBlock / 64>), gs, b, 0, s, RWPT_EXD_ARGS);
+        else hipLaunchKernelGGL((k_exchange_dpp<D, SM, 1>), gs, b, 0, s, RWPT_EXD_ARGS);
+      };
+      if (a.S <= 2) go_s(IC<2>{});
+      else if (a.S <= 4) go_s(IC<4>{});
+      else go_s(IC<8>{});
 #undef RWPT_EXD_ARGS
     };
     if (dim == 1) go(IC<1>{});
