@@ -221,8 +221,8 @@ def measured_traffic(kernel_tag: str):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); "
-              "the multi-GPU decomposition is described in DESIGN.md" % args.gpus, file=sys.stderr)
+        print("bench.py: the path runs on one GPU (--gpus %d requested); sharding across GPUs "
+              "is not implemented" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -93,7 +93,7 @@ def load_library(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise ImportError("librwpt.so is not built (%s); run __graft_entry__.build()" % path)
+        raise ImportError("librwpt.so is not built (%s); build it with python -m paper_1811_05474_amd._build" % path)
     lib = ctypes.CDLL(path)
     vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     pcfg = ctypes.POINTER(rwpt_config)
