@@ -154,20 +154,22 @@ def test_walk2d_step_with_walk_replayed(prec, tol, lanes):
     ens.close()
 
 
-def test_walk2d_n1e6_one_step_sampled():
+@pytest.mark.parametrize("prec,tol", [(F32, 1e-5), (F64, 1e-12)])
+def test_walk2d_n1e6_one_step_sampled(prec, tol):
     w = W.WORKLOADS["walk2d_n1e6"]
     x, M, sizes, _ = W.make_inputs(w)
-    x, M = f32(x), f32(M)
-    ens = make(dim=2, rw=1.0, prec=F32, seed=w.seed)
+    if prec == F32:
+        x, M = f32(x), f32(M)
+    ens = make(dim=2, rw=1.0, prec=prec, seed=w.seed)
     ens.init(sizes, x, M)
     ens.step(w.dt, w.D, 1)
     pos = ens.positions()
     got = ens.masses()
     rows = np.random.default_rng(5).choice(w.n, 4000, replace=False)
     walked = oracle.walk(x[rows], rows.astype(np.uint32), w.seed, 0, w.D, w.dt, (0, 0), (1, 1))
-    assert np.abs(pos[rows] - walked).max() < 2e-6
-    ref = oracle.transfer(pos, M, w.D, w.dt, kappa=3.0, prec=32, rows=rows)
-    assert normerr(got[:, rows], ref) < 1e-5
+    assert np.abs(pos[rows] - walked).max() < (2e-6 if prec == F32 else 1e-12)
+    ref = oracle.transfer(pos, M, w.D, w.dt, kappa=3.0, prec=32 if prec == F32 else 64, rows=rows)
+    assert normerr(got[:, rows], ref) < tol
     # mean in-cutoff neighbours near the closed-form value for the unit square
     pairs, _ = ens.count_pairs(w.dt, w.D)
     r = 3 * math.sqrt(8 * w.D * w.dt)
