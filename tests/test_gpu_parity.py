@@ -321,6 +321,24 @@ def test_walk3d_eight_species(prec, tol, lanes):
     ens.close()
 
 
+def test_walk3d_row_broadcast_tiles_whole_and_split():
+    """The binary32 row-broadcast kernels in 3-D, eight species: 80000
+    particles (5000 tiles, one wave per tile) and 40000 (2500 tiles, one block
+    per tile with the candidate chunks split over its four waves)."""
+    D, dt = 4e-5, 0.1
+    for n in (80000, 40000):
+        x = f32(W.positions(n, 3, 56))
+        M = f32(W.masses(n, 8, 56))
+        ens = make(dim=3, S=8, rw=1.0, prec=F32, seed=56, lanes=4)
+        ens.init([n], x, M)
+        ens.step(dt, D, 1)
+        assert ens.stats()["tile_lanes"] == 4
+        pos = ens.positions()
+        ref = oracle.transfer(pos, M, D, dt, kappa=3.0, prec=32)
+        assert normerr(ens.masses(), ref) < 1e-5, n
+        ens.close()
+
+
 @pytest.mark.parametrize("S", [1, 3, 5])
 def test_species_counts_and_no_reaction(S):
     n, D, dt = 5000, 1e-3, 0.1
