@@ -198,3 +198,12 @@ def test_probe_rate_validates_before_device(lib):
             assert ei.value.status == rwpt.RWPT_EDEVICE
     finally:
         rwpt.rwpt_destroy(ctx)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
