@@ -207,3 +207,18 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_init_refuses_more_particles_than_32_bit_indices(lib):
+    # sorted slots are 32-bit: the size check comes before any array is read,
+    # so the one-element buffers here are never touched
+    ctx = rwpt.rwpt_create(rwpt.rwpt_config_default())
+    try:
+        x = np.full((1, 2), 0.5)
+        M = np.ones((2, 1))
+        for sizes in ([2 ** 31], [2 ** 30, 2 ** 30], [2 ** 31 - 64]):
+            with pytest.raises(rwpt.RwptError) as ei:
+                rwpt.rwpt_init_ensemble(ctx, sizes, x, M)
+            assert ei.value.status == rwpt.RWPT_EINVAL and "too many particles" in str(ei.value)
+    finally:
+        rwpt.rwpt_destroy(ctx)
