@@ -6,9 +6,11 @@ Tolerances (normwise, max |dM| / max |M|):
     the hardware exp2, binary32 exchanges flushed into binary64 row partials);
   * neighbour lists: bit-exact (same binary32 / binary64 predicate);
   * conservation: FP64 path |d sum(A-B)| / sum(A+B) <= 1e-12, FP32 path <= 1e-6.
-Positions after a walk are compared to the oracle's walk within 2e-6 (binary32
-Box-Muller vs binary64), and the transfer is then checked on the positions the
-GPU stored (the oracle replays them).
+Steps with the walk are compared with the oracle's own trajectory (its walk,
+then its transfer, from its own previous state; tests/_oracle_steps.py): no
+oracle input comes from the GPU.  Positions agree within 2e-6 in the unit box
+(binary32 Box-Muller vs binary64, one binary32 ulp per move), and the masses
+within the bars above plus the effect of that ulp on the weights (walk_tol).
 """
 import math
 
@@ -18,6 +20,8 @@ import pytest
 import oracle
 from paper_1811_05474_amd import rwpt, workloads as W
 
+import _oracle_steps as OS
+
 pytestmark = pytest.mark.gpu
 
 F32 = rwpt.RWPT_FP32
@@ -26,6 +30,27 @@ F64 = rwpt.RWPT_FP64
 
 def f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def walk_tol(prec, D, dt, xmax=1.0, kappa=3.0):
+    """Normwise bar for a step that includes the walk, against the oracle's own
+    walk: the GPU and the oracle may place a particle one or two ulps apart
+    (u = ulp(xmax) in the path's precision), which changes a weight by up to
+    2 kappa u / sigma relative (sigma^2 = 8 D dt); an exchanged mass difference
+    is at most ~0.3 of the largest mass.  Added to the bar of the same step on
+    identical positions (1e-5 binary32, 1e-12 binary64)."""
+    u = float(np.spacing(np.float32(xmax))) if prec == F32 else float(np.spacing(np.float64(xmax)))
+    sigma = math.sqrt(8.0 * D * dt)
+    return (1e-5 if prec == F32 else 1e-12) + 0.3 * 2.0 * kappa * 2.0 * u / sigma
+
+
+def exact_sums(m, react=(0, 1)):
+    """Exactly rounded totals of a mass array: what the binary64 audit of those
+    masses must give (a property of the audit, not an oracle result)."""
+    sums = [math.fsum(m[s].tolist()) for s in range(m.shape[0])]
+    a, b = react
+    sums.append(math.fsum(m[a].tolist() + (-m[b]).tolist()))
+    return sums
 
 
 def normerr(a, b):
@@ -131,9 +156,9 @@ def test_neighbor_lists_bit_exact_2d(prec, lanes):
     ens.close()
 
 
-@pytest.mark.parametrize("prec,tol", [(F32, 1e-5), (F64, 1e-12)])
+@pytest.mark.parametrize("prec", [F32, F64])
 @pytest.mark.parametrize("lanes", [0, -1, 1, 4, 8, 16])
-def test_walk2d_step_with_walk_replayed(prec, tol, lanes):
+def test_walk2d_step_with_walk_replayed(prec, lanes):
     n, D, dt, seed = 30000, 2e-4, 0.1, 99
     x = W.positions(n, 2, seed)
     M = W.masses(n, 2, seed)
@@ -141,21 +166,16 @@ def test_walk2d_step_with_walk_replayed(prec, tol, lanes):
         x, M = f32(x), f32(M)
     ens = make(dim=2, rw=1.0, prec=prec, seed=seed, lanes=lanes)
     ens.init([n], x, M)
-    mcur, xcur = M, x
-    for step in range(3):
+    for step, (xr, mr) in enumerate(OS.steps(x, M, 3, D, dt, seed, (0, 0), (1, 1), prec == F32)):
         ens.step(dt, D, 1)
-        pos = ens.positions()
-        walked = oracle.walk(xcur, np.arange(n), seed, step, D, dt, (0, 0), (1, 1))
-        assert np.abs(pos - walked).max() < (2e-6 if prec == F32 else 1e-12)
-        ref = oracle.transfer(pos, mcur, D, dt, kappa=3.0, prec=32 if prec == F32 else 64)
+        assert np.abs(ens.positions() - xr).max() < (2e-6 if prec == F32 else 1e-12)
         got = ens.masses()
-        assert normerr(got, ref) < tol, normerr(got, ref)
-        mcur, xcur = got, pos
+        assert normerr(got, mr) < walk_tol(prec, D, dt), (step, normerr(got, mr))
     ens.close()
 
 
-@pytest.mark.parametrize("prec,tol", [(F32, 1e-5), (F64, 1e-12)])
-def test_walk2d_n1e6_one_step_sampled(prec, tol):
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_walk2d_n1e6_one_step_sampled(prec):
     w = W.WORKLOADS["walk2d_n1e6"]
     x, M, sizes, _ = W.make_inputs(w)
     if prec == F32:
@@ -166,10 +186,9 @@ def test_walk2d_n1e6_one_step_sampled(prec, tol):
     pos = ens.positions()
     got = ens.masses()
     rows = np.random.default_rng(5).choice(w.n, 4000, replace=False)
-    walked = oracle.walk(x[rows], rows.astype(np.uint32), w.seed, 0, w.D, w.dt, (0, 0), (1, 1))
-    assert np.abs(pos[rows] - walked).max() < (2e-6 if prec == F32 else 1e-12)
-    ref = oracle.transfer(pos, M, w.D, w.dt, kappa=3.0, prec=32 if prec == F32 else 64, rows=rows)
-    assert normerr(got[:, rows], ref) < tol
+    (xr, ref), = OS.steps(x, M, 1, w.D, w.dt, w.seed, (0, 0), (1, 1), prec == F32, rows=rows)
+    assert np.abs(pos - xr).max() < (2e-6 if prec == F32 else 1e-12)
+    assert normerr(got[:, rows], ref) < walk_tol(prec, w.D, w.dt)
     # mean in-cutoff neighbours near the closed-form value for the unit square
     pairs, _ = ens.count_pairs(w.dt, w.D)
     r = 3 * math.sqrt(8 * w.D * w.dt)
@@ -179,8 +198,8 @@ def test_walk2d_n1e6_one_step_sampled(prec, tol):
     ens.close()
 
 
-@pytest.mark.parametrize("prec,tol", [(F32, 1e-5), (F64, 1e-12)])
-def test_walk3d_n8e6_one_step_sampled(prec, tol):
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_walk3d_n8e6_one_step_sampled(prec):
     """The 3-D, eight-species workload at full size (8e6 particles) in the
     tiling the benchmark times (one lane per particle): one step, sampled
     particles against the oracle, and the pair count against the closed form."""
@@ -195,10 +214,9 @@ def test_walk3d_n8e6_one_step_sampled(prec, tol):
     pos = ens.positions()
     got = ens.masses()
     rows = np.random.default_rng(6).choice(w.n, 4000, replace=False)
-    walked = oracle.walk(x[rows], rows.astype(np.uint32), w.seed, 0, w.D, w.dt, (0, 0, 0), (1, 1, 1))
-    assert np.abs(pos[rows] - walked).max() < (2e-6 if prec == F32 else 1e-12)
-    ref = oracle.transfer(pos, M, w.D, w.dt, kappa=3.0, prec=32 if prec == F32 else 64, rows=rows)
-    assert normerr(got[:, rows], ref) < tol
+    (xr, ref), = OS.steps(x, M, 1, w.D, w.dt, w.seed, (0, 0, 0), (1, 1, 1), prec == F32, rows=rows)
+    assert np.abs(pos - xr).max() < (2e-6 if prec == F32 else 1e-12)
+    assert normerr(got[:, rows], ref) < walk_tol(prec, w.D, w.dt)
     # ordered pairs: n (n - 1) F(r) with the unit-cube pair-distance CDF
     # F(r) = 4 pi r^3 / 3 - 3 pi r^4 / 2 + 8 r^5 / 5 - r^6 / 6 (r <= 1)
     pairs, _ = ens.count_pairs(w.dt, w.D)
@@ -221,7 +239,7 @@ def test_walk2d_n1e6_conservation_over_steps():
         assert abs(a1[2] - a0[2]) / (a0[0] + a0[1]) < tol
         m = ens.masses()
         assert np.all(np.minimum(m[0], m[1]) == 0.0)
-        exact = oracle.audit(m)
+        exact = exact_sums(m)
         assert abs(exact[2] - a1[2]) <= 1e-12 * (a0[0] + a0[1])
         ens.close()
 
@@ -243,7 +261,7 @@ def test_batched_realisations_match_independent_oracles():
         b, e = off[r], off[r + 1]
         ref = oracle_run(x[b:e], M[:, b:e], Ds[r], w.dt, 2, 3.0, 32)
         assert normerr(got[:, b:e], ref) < 1e-5, r
-        assert abs(a[r, 0] - oracle.audit(got[:, b:e])[0]) < 1e-12
+        assert abs(a[r, 0] - exact_sums(got[:, b:e])[0]) < 1e-12
     ens.close()
 
 
@@ -265,10 +283,12 @@ def test_batch2d_64_full_size_sampled():
     for r in [int(order[0]), int(order[1]), int(order[-1]), int(order[-2]), 10, 11]:
         b, e = int(off[r]), int(off[r + 1])
         rows = rng.choice(e - b, min(400, e - b), replace=False)
-        walked = oracle.walk(x[b + rows], (b + rows).astype(np.uint32), w.seed, 0, Ds[r], w.dt, (0, 0), (1, 1))
-        assert np.abs(pos[b + rows] - walked).max() < 2e-6, r
-        ref = oracle.transfer(pos[b:e], M[:, b:e], Ds[r], w.dt, kappa=3.0, prec=32, rows=rows)
-        assert normerr(got[:, b + rows], ref) < 1e-5, r
+        # realisation r alone: its particles keep their global Philox ids
+        walked = oracle.walk(x[b:e], np.arange(b, e, dtype=np.uint32), w.seed, 0, Ds[r], w.dt, (0, 0), (1, 1))
+        xr = f32(walked)
+        assert np.abs(pos[b:e] - xr).max() < 2e-6, r
+        ref = oracle.transfer(xr, M[:, b:e], Ds[r], w.dt, kappa=3.0, prec=32, rows=rows)
+        assert normerr(got[:, b + rows], ref) < walk_tol(F32, Ds[r], w.dt), r
     ens.close()
 
 
@@ -294,9 +314,9 @@ def test_batch_with_empty_and_single_realisations():
 
 # --------------------------------------------------------------------- 3-D ----
 
-@pytest.mark.parametrize("prec,tol", [(F32, 1e-5), (F64, 1e-12)])
+@pytest.mark.parametrize("prec", [F32, F64])
 @pytest.mark.parametrize("lanes", [0, -1, 4])
-def test_walk3d_eight_species(prec, tol, lanes):
+def test_walk3d_eight_species(prec, lanes):
     n, D, dt = 50000, 4e-5, 0.1
     x = W.positions(n, 3, 55)
     M = W.masses(n, 8, 55)
@@ -304,15 +324,17 @@ def test_walk3d_eight_species(prec, tol, lanes):
         x, M = f32(x), f32(M)
     ens = make(dim=3, S=8, rw=1.0, prec=prec, seed=55, lanes=lanes)
     ens.init([n], x, M)
-    ens.step(dt, D, 1)
-    pos = ens.positions()
-    ref = oracle.transfer(pos, M, D, dt, kappa=3.0, prec=32 if prec == F32 else 64)
-    assert normerr(ens.masses(), ref) < tol
+    # neighbour sets and counts on the initial positions (the same input on both sides)
     rp, cols = ens.neighbors(dt, D)
-    rp0, cols0 = oracle.neighbors(pos, 3.0, D, dt, 32 if prec == F32 else 64)
+    rp0, cols0 = oracle.neighbors(x, 3.0, D, dt, 32 if prec == F32 else 64)
     assert np.array_equal(rp, rp0) and np.array_equal(cols, cols0)
     pairs, evals = ens.count_pairs(dt, D)
     assert pairs == rp0[-1] - n and evals >= rp0[-1]
+    # one step with the walk against the oracle's own step
+    ens.step(dt, D, 1)
+    (xr, mr), = OS.steps(x, M, 1, D, dt, 55, (0, 0, 0), (1, 1, 1), prec == F32)
+    assert np.abs(ens.positions() - xr).max() < (2e-6 if prec == F32 else 1e-12)
+    assert normerr(ens.masses(), mr) < walk_tol(prec, D, dt)
     if ens.stats()["tile_lanes"] == -1:
         # one lane per particle: only the cells of its own cutoff box (about
         # 2 x 2 x 2 cells of two cutoffs, ~16 candidates here for ~2 neighbours
@@ -333,9 +355,9 @@ def test_walk3d_row_broadcast_tiles_whole_and_split():
         ens.init([n], x, M)
         ens.step(dt, D, 1)
         assert ens.stats()["tile_lanes"] == 4
-        pos = ens.positions()
-        ref = oracle.transfer(pos, M, D, dt, kappa=3.0, prec=32)
-        assert normerr(ens.masses(), ref) < 1e-5, n
+        (xr, mr), = OS.steps(x, M, 1, D, dt, 56, (0, 0, 0), (1, 1, 1), True)
+        assert np.abs(ens.positions() - xr).max() < 2e-6, n
+        assert normerr(ens.masses(), mr) < walk_tol(F32, D, dt), n
         ens.close()
 
 
@@ -468,11 +490,10 @@ def test_autotune_restores_state_and_keeps_parity(tmp_path, monkeypatch):
     lanes, ref = rwpt.rwpt_get_tiling(ens.ctx)
     assert lanes in (1, 4, 8, 16)
     ens.step(dt, D, 1)
-    pos = ens.positions()
-    walked = oracle.walk(p0, np.arange(n), 41, s0, D, dt, (0, 0), (1, 1))
-    assert np.abs(pos - walked).max() < 2e-6
-    ref_m = oracle.transfer(pos, m0, D, dt, kappa=3.0, prec=32)
-    assert normerr(ens.masses(), ref_m) < 1e-5
+    # the tuned context continues the oracle's own three-step trajectory
+    xr, mr = list(OS.steps(f32(x), f32(M), 3, D, dt, 41, (0, 0), (1, 1), True))[-1]
+    assert np.abs(ens.positions() - xr).max() < 2e-6
+    assert normerr(ens.masses(), mr) < walk_tol(F32, D, dt)
     ens.close()
     # a second context with the same shape takes the cached choice
     text = (tmp_path / "tune.txt").read_text()
@@ -524,7 +545,7 @@ def test_dense_plain1d_n32768_two_steps_and_walk():
     ref = oracle_run(x, M, w.D, w.dt, 2, math.inf, 32)
     assert normerr(ens.masses(), ref) < 1e-5
     ens.close()
-    # with the walk, the transfer is checked on the positions the GPU stored
+    # with the walk: one step against the oracle's own walk + full-matrix transfer
     n = 6000
     x = f32(W.positions(n, 2, 9))
     M = f32(W.masses(n, 2, 9))
@@ -532,9 +553,9 @@ def test_dense_plain1d_n32768_two_steps_and_walk():
                         path=rwpt.RWPT_PATH_DENSE, seed=9)
     ens.init([n], x, M)
     ens.step(0.1, 1e-3, 1)
-    pos = ens.positions()
-    ref = oracle.transfer(pos, M, 1e-3, 0.1, kappa=math.inf, prec=32)
-    assert normerr(ens.masses(), ref) < 1e-5
+    (xr, mr), = OS.steps(x, M, 1, 1e-3, 0.1, 9, (0, 0), (1, 1), True, kappa=math.inf)
+    assert np.abs(ens.positions() - xr).max() < 2e-6
+    assert normerr(ens.masses(), mr) < walk_tol(F32, 1e-3, 0.1)
     ens.close()
 
 
@@ -559,29 +580,25 @@ def interface_ensemble(n, n_real, seed0):
     return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts], 1)
 
 
-@pytest.mark.parametrize("prec,tol", [(F32, 1e-5), (F64, 1e-12)])
-def test_interface_steps_replayed(prec, tol):
-    # three realisations with the walk: each step's walk against the oracle's
-    # walk (global particle ids), the transfer on the positions the GPU stored
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_interface_steps_replayed(prec):
+    # three realisations with the walk, four steps against the oracle's own
+    # trajectory (global particle ids).  Binary32 positions up to 50 resolve
+    # 3.8e-6, so the two trajectories drift apart by a few such units
     n, R, seed = 2000, 3, 6000
     x, M = interface_ensemble(n, R, seed)
     if prec == F32:
         x, M = f32(x), f32(M)
     ens = make(dim=1, react=None, rw=1.0, prec=prec, seed=seed, box_hi=(50.0, 1, 1))
     ens.init([n] * R, x, M)
-    xcur, mcur = x, M
-    for step in range(4):
+    traj = OS.steps(x, M, 4, 0.5, 0.1, seed, (0.0,), (50.0,), prec == F32, sizes=[n] * R, react=None)
+    for step, (xr, mr) in enumerate(traj):
         ens.step(0.1, 0.5, 1)
         pos, got = ens.positions(), ens.masses()
-        walked = oracle.walk(xcur, np.arange(n * R), seed, step, 0.5, 0.1, (0.0,), (50.0,))
-        # binary32 positions up to 50 carry 2e-6 relative rounding per move
-        assert np.abs(pos - walked).max() < (1e-4 if prec == F32 else 1e-12)
-        for r in range(R):
-            b, e = r * n, (r + 1) * n
-            ref = oracle.transfer(pos[b:e], mcur[:, b:e], 0.5, 0.1, kappa=3.0,
-                                  prec=32 if prec == F32 else 64, react=None)
-            assert normerr(got[:, b:e], ref) < tol, (step, r)
-        xcur, mcur = pos, got
+        assert np.abs(pos - xr).max() < (1e-4 if prec == F32 else 1e-12)
+        errs = [normerr(got[:, r * n:(r + 1) * n], mr[:, r * n:(r + 1) * n]) for r in range(R)]
+        print("step", step, "max position difference %.2e" % np.abs(pos - xr).max(), "mass errors", errs)
+        assert max(errs) < walk_tol(prec, 0.5, 0.1, xmax=50.0), (step, errs)
     ens.close()
 
 
@@ -624,8 +641,8 @@ def test_interface1d_l50_matches_erfc(prec):
 
 @pytest.mark.parametrize("dim", [1, 2, 3])
 @pytest.mark.parametrize("mean_nb", [0.7, 2.5, 6.0, 12.0])
-@pytest.mark.parametrize("prec,tol,norm", [(F32, 1e-5, rwpt.RWPT_NORM_SYM), (F64, 1e-12, rwpt.RWPT_NORM_ROW)])
-def test_private_lists_cached_and_missed_neighbours(dim, mean_nb, prec, tol, norm):
+@pytest.mark.parametrize("prec,norm", [(F32, rwpt.RWPT_NORM_SYM), (F64, rwpt.RWPT_NORM_ROW)])
+def test_private_lists_cached_and_missed_neighbours(dim, mean_nb, prec, norm):
     # mean in-cutoff neighbours per particle from 0.7 (every lane cached) to 12
     # (most lanes above the per-lane limit of 8, waves beyond their region):
     # cached lanes, missed lanes and mixed waves must all match the oracle
@@ -640,16 +657,12 @@ def test_private_lists_cached_and_missed_neighbours(dim, mean_nb, prec, tol, nor
     lo, hi = (0.0,) * dim, (1.0,) * dim
     ens = make(dim=dim, rw=1.0, prec=prec, norm=norm, seed=seed, lanes=-1)
     ens.init([n], x, M)
-    mcur, xcur = M, x
     onorm = oracle.NORM_SYM if norm == rwpt.RWPT_NORM_SYM else oracle.NORM_ROW
-    for step in range(2):
+    for step, (xr, mr) in enumerate(OS.steps(x, M, 2, D, dt, seed, lo, hi, prec == F32, norm=onorm)):
         ens.step(dt, D, 1)
         pos, got = ens.positions(), ens.masses()
-        walked = oracle.walk(xcur, np.arange(n), seed, step, D, dt, lo, hi)
-        assert np.abs(pos - walked).max() < (2e-6 if prec == F32 else 1e-12)
-        ref = oracle.transfer(pos, mcur, D, dt, kappa=3.0, norm=onorm, prec=32 if prec == F32 else 64)
-        assert normerr(got, ref) < tol, (step, normerr(got, ref))
-        mcur, xcur = got, pos
+        assert np.abs(pos - xr).max() < (2e-6 if prec == F32 else 1e-12)
+        assert normerr(got, mr) < walk_tol(prec, D, dt), (step, normerr(got, mr))
     pairs, _ = ens.count_pairs(dt, D)
     assert 0.5 * mean_nb * n < pairs < 1.5 * mean_nb * n
     ens.close()
@@ -744,8 +757,8 @@ def test_dense_full_matrix_at_its_maximum_size():
 # ------------------------------------------- advection and dispersion (Eq. 1) ----
 
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("prec,tol", [(F32, 1e-5), (F64, 1e-12)])
-def test_advective_walk_replayed(dim, prec, tol):
+@pytest.mark.parametrize("prec", [F32, F64])
+def test_advective_walk_replayed(dim, prec):
     n, D, dt, seed = 20000, 1e-4, 0.1, 123
     vel = (0.02, -0.015, 0.01)[:dim]
     aL, aT = 0.01, 0.002
@@ -757,15 +770,12 @@ def test_advective_walk_replayed(dim, prec, tol):
     ens = rwpt.Ensemble(dim=dim, n_species=2, rw_ratio=1.0, precision=prec, seed=seed, velocity=vel,
                         alpha_l=aL, alpha_t=aT)
     ens.init([n], x, M)
-    xcur, mcur = x, M
-    for step in range(3):
+    traj = OS.steps(x, M, 3, D, dt, seed, lo, hi, prec == F32, velocity=vel, alpha_l=aL, alpha_t=aT)
+    for step, (xr, mr) in enumerate(traj):
         ens.step(dt, D, 1)
         pos, got = ens.positions(), ens.masses()
-        walked = oracle.walk(xcur, np.arange(n), seed, step, D, dt, lo, hi, velocity=vel, alpha_l=aL, alpha_t=aT)
-        assert np.abs(pos - walked).max() < (2e-6 if prec == F32 else 1e-12)
-        ref = oracle.transfer(pos, mcur, D, dt, kappa=3.0, prec=32 if prec == F32 else 64)
-        assert normerr(got, ref) < tol, (step, normerr(got, ref))
-        xcur, mcur = pos, got
+        assert np.abs(pos - xr).max() < (2e-6 if prec == F32 else 1e-12)
+        assert normerr(got, mr) < walk_tol(prec, D, dt), (step, normerr(got, mr))
     ens.close()
 
 
@@ -802,16 +812,16 @@ def test_interface2d_l80_matches_erfc(prec):
     x, M, sizes, _ = W.make_inputs(w)
     ens = make(dim=2, react=None, rw=w.rw_ratio, prec=prec, seed=w.seed, box_hi=w.box_hi)
     ens.init(sizes, x, M)
-    # the first steps replayed against the oracle (realisation 0)
-    xcur, mcur = (f32(x[:n]), f32(M[:, :n])) if prec == F32 else (x[:n], M[:, :n])
-    for step in range(2):
+    # the first steps against the oracle's own trajectory (realisation 0)
+    x0, m0 = (f32(x[:n]), f32(M[:, :n])) if prec == F32 else (x[:n], M[:, :n])
+    traj = OS.steps(x0, m0, 2, w.D, w.dt, w.seed, (0, 0), (L, L), prec == F32, react=None)
+    for step, (xr, mr) in enumerate(traj):
         ens.step(w.dt, w.D, 1)
         pos, got = ens.positions()[:n], ens.masses()[:, :n]
-        walked = oracle.walk(xcur, np.arange(n), w.seed, step, w.D, w.dt, (0, 0), (L, L))
-        assert np.abs(pos - walked).max() < (2e-4 if prec == F32 else 1e-11)
-        ref = oracle.transfer(pos, mcur, w.D, w.dt, kappa=3.0, prec=32 if prec == F32 else 64, react=None)
-        assert normerr(got, ref) < (1e-5 if prec == F32 else 1e-12)
-        xcur, mcur = pos, got
+        assert np.abs(pos - xr).max() < (2e-4 if prec == F32 else 1e-11)
+        err = normerr(got, mr)
+        print("step", step, "max position difference %.2e" % np.abs(pos - xr).max(), "mass error %.2e" % err)
+        assert err < walk_tol(prec, w.D, w.dt, xmax=L)
     ens.step(w.dt, w.D, w.steps - 2)
     pos, got = ens.positions(), ens.masses()
     ds = L * L / n
