@@ -175,7 +175,10 @@ static int default_lanes(int dim, int64_t n, bool fp64) {
   // particle (32768 particles: exchange 37 vs 54 us)
   if (dim == 1) return fp64 ? 16 : 4;
   if (dim == 3) return -1;  // sparse neighbourhoods: private candidate rows
-  // 4 lanes per particle uses the row-broadcast (DPP) kernels in binary32
+  // binary32: the row-broadcast kernels at every size (below 4097 tiles each
+  // tile takes a whole block); ~225 neighbours per particle, 2e4 - 3e5
+  // particles: 0.054 vs 0.058 ms (4 vs 8 lanes) at 2e4, 0.104 vs 0.140 at 1.5e5
+  if (!fp64) return 4;
   return n >= (int64_t)1 << 18 ? 4 : 8;
 }
 
