@@ -309,18 +309,24 @@ def main():
     flops_per_launch = exchange_flops_per_pair(w.dim, w.n_species) * alg_pairs
     achieved_tflops = flops_per_launch / (ex["us_avg"] * 1e-6) / 1e12
     alg_bytes = exchange_bytes_per_particle(w.dim, w.n_species, 4) * n_total
+    achieved_gbps = alg_bytes / (ex["us_avg"] * 1e-6) / 1e9
+    # the roof the kernel's algorithmic intensity puts it under: flops per
+    # algorithmic byte against the machine balance (peak flops / peak bytes)
+    hbm_bound = flops_per_launch < alg_bytes * (PEAK_FP32_VECTOR_TFLOPS * 1e12) / (PEAK_HBM_GBPS * 1e9)
     roofline = {
-        "bound": "alu",
+        "bound": "hbm" if hbm_bound else "alu",
         "kernel": kernel,
-        "achieved": achieved_tflops,
-        "peak": PEAK_FP32_VECTOR_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": achieved_tflops / PEAK_FP32_VECTOR_TFLOPS,
+        "achieved": achieved_gbps if hbm_bound else achieved_tflops,
+        "peak": PEAK_HBM_GBPS if hbm_bound else PEAK_FP32_VECTOR_TFLOPS,
+        "unit": "GB/s" if hbm_bound else "TFLOP/s",
+        "frac": achieved_gbps / PEAK_HBM_GBPS if hbm_bound else achieved_tflops / PEAK_FP32_VECTOR_TFLOPS,
         "traffic": measured_traffic(("k_dense_exchange_" if dense else "k_exchange_") + w.name),
         "us_per_launch": ex["us_avg"],
         "flops_per_launch": flops_per_launch,
         "algorithmic_bytes_per_launch": alg_bytes,
-        "hbm_frac_of_algorithmic_bytes": alg_bytes / (ex["us_avg"] * 1e-6) / 1e9 / PEAK_HBM_GBPS,
+        "flops_per_algorithmic_byte": flops_per_launch / alg_bytes,
+        "hbm_frac_of_algorithmic_bytes": achieved_gbps / PEAK_HBM_GBPS,
+        "alu_frac_of_algorithmic_flops": achieved_tflops / PEAK_FP32_VECTOR_TFLOPS,
     }
     if dense:
         roofline["ordered_pairs_evaluated_per_launch"] = alg_pairs
