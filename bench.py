@@ -18,6 +18,16 @@ the 1-D full matrix on matrix cores.  For the full matrix the pair count is
 every pair of the realisation, and the roofline counts the pairs whose weight
 is at least 2^-40 (separation within sqrt(40 ln 2) sigma), the ones the kernel
 must evaluate to binary32 accuracy.
+
+Besides value, the line carries: roofline (the exchange kernel against the
+FP32 vector peak, or against HBM when its flops per algorithmic byte are
+below the machine balance; traffic from the committed rocprofv3 counter
+summary while the device sources match it), step_roofline (the whole step's
+algorithmic bytes against HBM), valu_probe (the row-broadcast pair kernels'
+evaluation rates against register-only kernels running the same
+per-candidate code, rwpt_probe_rate), host_io (one step fed from and returned
+to host memory, PCIe included), fp64 (the same run in binary64) and
+cpu_baseline (the CPU oracle on a bounded sample of the same workload).
 """
 from __future__ import annotations
 
