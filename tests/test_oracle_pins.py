@@ -223,6 +223,22 @@ def test_expected_pair_count_in_unit_square():
     assert abs(pairs - mean) < 6 * math.sqrt(mean * (1 + 4 * n * math.pi * r * r))
 
 
+@pytest.mark.parametrize("n,r", [(20000, 0.05), (3000, 0.3)])
+def test_expected_pair_count_in_unit_cube(n, r):
+    # The same in the unit cube: F3(r) = 4 pi r^3 / 3 - 3 pi r^4 / 2 + 8 r^5 / 5
+    # - r^6 / 6 (r <= 1, from integrating (1 - |u1|)(1 - |u2|)(1 - |u3|) over
+    # the ball of radius r).  At r = 0.3 the r^4 wall term shifts the count by
+    # about 1.5 bounds, so a formula without it fails.
+    dt = 0.1
+    D = r * r / (72.0 * dt)  # cutoff 3 sqrt(8 D dt) = r
+    x = W.positions(n, 3, 78)
+    rowptr, _ = oracle.neighbors(x, 3.0, D, dt, 64)
+    pairs = (rowptr[-1] - n) / 2
+    F = 4 * math.pi * r ** 3 / 3 - 1.5 * math.pi * r ** 4 + 1.6 * r ** 5 - r ** 6 / 6
+    mean = n * (n - 1) / 2 * F
+    assert abs(pairs - mean) < 6 * math.sqrt(mean * (1 + 4 * n * F))
+
+
 # ------------------------------------------------------ paper arithmetic ----
 
 def test_pad_ratios_printed_in_the_paper():
