@@ -194,7 +194,8 @@ def test_walk2d_n1e6_one_step_sampled(prec):
     r = 3 * math.sqrt(8 * w.D * w.dt)
     F = math.pi * r * r - 8 * r ** 3 / 3 + r ** 4 / 2
     expect = w.n * (w.n - 1) * F
-    assert abs(pairs - expect) < 6 * math.sqrt(expect * 500)
+    # ordered pairs: variance ~ 2 E (1 + 4 n F) (pairs sharing a particle correlate)
+    assert abs(pairs - expect) < 6 * math.sqrt(2 * expect * (1 + 4 * w.n * F))
     ens.close()
 
 
@@ -223,7 +224,7 @@ def test_walk3d_n8e6_one_step_sampled(prec):
     r = 3 * math.sqrt(8 * w.D * w.dt)
     F = 4 * math.pi * r ** 3 / 3 - 1.5 * math.pi * r ** 4 + 1.6 * r ** 5 - r ** 6 / 6
     expect = w.n * (w.n - 1) * F
-    assert abs(pairs - expect) < 6 * math.sqrt(4 * expect)
+    assert abs(pairs - expect) < 6 * math.sqrt(2 * expect * (1 + 4 * w.n * F))
     ens.close()
 
 
