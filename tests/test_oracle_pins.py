@@ -133,6 +133,21 @@ def test_sym_conserves_mass_and_row_does_not():
     assert np.max(np.abs(oracle.audit(Mr, None)[:2] - tot0) / tot0) > 1e-6
 
 
+def test_sym_conserves_mass_over_a_walked_run():
+    # Sec. 2.1: the symmetric exchange moves mass between pairs only, so the
+    # totals of a walk + transfer run stay put to rounding (no reaction).
+    n = 600
+    x = W.positions(n, 2, 31)
+    M = W.masses(n, 2, 31)
+    ids = np.arange(n, dtype=np.uint32)
+    tot0 = oracle.audit(M, None)[:2]
+    for k in range(40):
+        x = oracle.walk(x, ids, 77, k, 5e-4, 0.1, lo=(0, 0), hi=(1, 1))
+        M = oracle.transfer(x, M, 5e-4, 0.1, kappa=3.0, norm=oracle.NORM_SYM, prec=64, react=None)
+    assert np.all(np.abs(oracle.audit(M, None)[:2] - tot0) <= 1e-12 * tot0)
+    assert np.max(np.abs(M - W.masses(n, 2, 31))) > 1e-2 * np.max(M)
+
+
 def test_transfer_is_linear_in_mass():
     x, M = _case()
     M2 = W.masses(800, 2, 99)
@@ -147,6 +162,21 @@ def test_permutation_equivariance():
     out = oracle.transfer(x, M, 3e-3, 0.1, kappa=3.0, prec=32)
     outp = oracle.transfer(x[perm], M[:, perm], 3e-3, 0.1, kappa=3.0, prec=32)
     assert np.allclose(outp, out[:, perm], rtol=1e-13, atol=1e-19)
+
+
+@pytest.mark.parametrize("norm", [oracle.NORM_SYM, oracle.NORM_ROW])
+def test_translation_invariance(norm):
+    # Eqs. (3)-(6) see positions only through separations.  On a 2^-20 grid
+    # both the shift and every separation are exact in binary64, so no pair
+    # can cross the cutoff; only the order of the sums may change.
+    n, d = 700, 3
+    x = np.floor(W.positions(n, d, 8) * 2.0 ** 20) / 2.0 ** 20
+    M = W.masses(n, 2, 8)
+    shift = np.array([0.375, -0.25, 3.5])
+    out = oracle.transfer(x, M, 2e-3, 0.1, kappa=3.0, norm=norm, prec=64)
+    outs = oracle.transfer(x + shift, M, 2e-3, 0.1, kappa=3.0, norm=norm, prec=64)
+    assert np.max(np.abs(out - M)) > 1e-3 * np.max(M)
+    assert np.allclose(outs, out, rtol=1e-13, atol=1e-19)
 
 
 def test_cutoff_converges_to_full_matrix():
