@@ -79,7 +79,9 @@ hipError_t launch_nbr_fill(int fp64, int dim, int log2l, const PairArgs& a, hipS
 // then the chunks of each realisation) in one launch; `done` holds n_real + 1
 // zeroed completion counters that the kernel returns to zero.  Optionally
 // advances the step counter.
-constexpr int kAuditChunk = 1024;
+// Few, large chunks: every chunk block ends in a device-scope fence and
+// completion atomics on shared counters, which serialise across blocks.
+constexpr int kAuditChunk = 2048;
 hipError_t launch_audit_reduce(const double* part, int32_t S1, const int2* chunks, int32_t nchunks,
                                double* chunk_part, const int32_t* chunk_start, int32_t n_real,
                                double* out, uint32_t* done, uint64_t* step_ctr, int32_t bump,

@@ -1510,19 +1510,41 @@ __global__ __launch_bounds__(kBlock) void k_nbr(PairArgs a) {
 // Audit
 // ---------------------------------------------------------------------------
 
-// Fixed-order block sum of v over the 256 threads (thread 0 gets the result).
 constexpr int kAuditValues = 9;  // S + 1 audit values for at most eight species
 
+// Fixed-order sum over the block of acc[0 .. S1): recursive halving inside
+// each wave, then the waves added in wave order through LDS.  Thread v < S1
+// gets the total of value v; the others get 0.  Every thread must call it.
+template <int NV>
+__device__ __forceinline__ double block_sum_fixed(double (&acc)[NV], double (*sh)[NV], int S1) {
+  constexpr int NK = halved_count(NV, 64);
+  constexpr int NB = halving_bits(NV, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int idx = 0, real = NV;
+  halve_sum<1, 64, NV, NV>(acc, idx, real, lane);
+#pragma unroll
+  for (int k = 0; k < NK; ++k)
+    if (k < real && lane < (1 << NB)) sh[wave][idx + k] = acc[k];
+  __syncthreads();
+  double c = 0.0;
+  if ((int)threadIdx.x < S1) {
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) c += sh[w][threadIdx.x];
+  }
+  __syncthreads();  // sh may be reused on return
+  return c;
+}
+
 // Audit in one launch: every block sums one chunk of at most kAuditChunk
-// consecutive tiles (never straddling realisations) in a fixed order -- each
-// thread its strided tiles, then the waves by recursive halving, then the
-// block's waves in wave order.  The block that completes a realisation's last
-// chunk (counter done[1 + r]) sums that realisation's chunk partials in chunk
-// order with one wave (lanes over chunks, then recursive halving), so
-// realisations are finalised in parallel and the result does not depend on
-// which block finishes last.  The block that completes the last chunk overall
-// (counter done[0]) advances the step counter.  Every counter is returned to
-// zero for the next launch (no memset node, so the launch can be captured).
+// consecutive tiles (never straddling realisations; each thread loads all of
+// its kAuditChunk / kBlock tiles at once) in a fixed order.  The block that
+// completes a realisation's last chunk (counter done[1 + r]) sums that
+// realisation's chunk partials in chunk order (threads over chunks, then the
+// same fixed-order block sum), so realisations are finalised in parallel and
+// the result does not depend on which block finishes last.  The block that
+// completes the last chunk overall (counter done[0]) advances the step
+// counter.  Every counter is returned to zero for the next launch (no memset
+// node, so the launch can be captured).
 __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ part, int32_t S1,
                                                   const int2* __restrict__ chunks, int32_t nchunks,
                                                   double* __restrict__ chunk_part,
@@ -1530,33 +1552,28 @@ __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ par
                                                   double* __restrict__ out, uint32_t* __restrict__ done,
                                                   uint64_t* __restrict__ step_ctr, int32_t bump) {
   constexpr int NV = kAuditValues;
-  constexpr int NK = halved_count(NV, 64);
-  constexpr int NB = halving_bits(NV, 64);
   __shared__ double sh[kBlock / 64][NV];
   __shared__ int last_r;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int2 ch = chunks[blockIdx.x];
+  // every load of the thread's tiles first, then the sums in tile order
+  constexpr int U = kAuditChunk / kBlock;
+  double val[U][NV];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int t = ch.x + (int)threadIdx.x + u * kBlock;
+    const double* pt = part + (int64_t)t * S1;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) val[u][v] = (t < ch.y && v < S1) ? pt[v] : 0.0;
+  }
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  for (int t = ch.x + threadIdx.x; t < ch.y; t += kBlock) {
-    const double* pt = part + (int64_t)t * S1;
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-      if (v < S1) acc[v] += pt[v];
-  }
-  int idx = 0, real = NV;
-  halve_sum<1, 64, NV, NV>(acc, idx, real, lane);
+  for (int u = 0; u < U; ++u)
 #pragma unroll
-  for (int k = 0; k < NK; ++k)
-    if (k < real && lane < (1 << NB)) sh[wave][idx + k] = acc[k];
-  __syncthreads();
-  if (threadIdx.x < S1) {
-    double c = 0.0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) c += sh[w][threadIdx.x];
-    chunk_part[(int64_t)blockIdx.x * S1 + threadIdx.x] = c;
-  }
+    for (int v = 0; v < NV; ++v) acc[v] += val[u][v];
+  const double c = block_sum_fixed<NV>(acc, sh, S1);
+  if ((int)threadIdx.x < S1) chunk_part[(int64_t)blockIdx.x * S1 + threadIdx.x] = c;
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1571,25 +1588,22 @@ __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ par
     last_r = atomicAdd(&done[1 + lo], 1u) == nch - 1 ? lo : -1;
   }
   __syncthreads();
-  const int r = last_r;
-  if (r >= 0 && wave == 0) {
+  const int r = last_r;  // the same in every thread of the block
+  if (r >= 0) {
     __threadfence();
     const int c0 = chunk_start[r], c1 = chunk_start[r + 1];
     double a[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) a[v] = 0.0;
-    for (int c = c0 + lane; c < c1; c += 64) {
+    for (int k = c0 + (int)threadIdx.x; k < c1; k += kBlock) {
 #pragma unroll
       for (int v = 0; v < NV; ++v)
         if (v < S1)
-          a[v] += __hip_atomic_load(&chunk_part[(int64_t)c * S1 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          a[v] += __hip_atomic_load(&chunk_part[(int64_t)k * S1 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    int ri = 0, rr = NV;
-    halve_sum<1, 64, NV, NV>(a, ri, rr, lane);
-#pragma unroll
-    for (int k = 0; k < NK; ++k)
-      if (k < rr && lane < (1 << NB) && ri + k < S1) out[(int64_t)r * S1 + ri + k] = a[k];
-    if (lane == 0) done[1 + r] = 0u;
+    const double tot = block_sum_fixed<NV>(a, sh, S1);
+    if ((int)threadIdx.x < S1) out[(int64_t)r * S1 + threadIdx.x] = tot;
+    if (threadIdx.x == 0) done[1 + r] = 0u;
   }
   if (threadIdx.x == 0 && atomicAdd(&done[0], 1u) == (uint32_t)(nchunks - 1)) {
     done[0] = 0u;
