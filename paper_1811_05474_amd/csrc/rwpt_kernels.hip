@@ -1539,8 +1539,8 @@ __device__ __forceinline__ double block_sum_fixed(double (&acc)[NV], double (*sh
 // consecutive tiles (never straddling realisations; each thread loads all of
 // its kAuditChunk / kBlock tiles at once) in a fixed order.  The block that
 // completes a realisation's last chunk (counter done[1 + r]) sums that
-// realisation's chunk partials in chunk order (threads over chunks, then the
-// same fixed-order block sum), so realisations are finalised in parallel and
+// realisation's chunk partials in chunk order with one wave (lanes over
+// chunks, then recursive halving), so realisations are finalised in parallel and
 // the result does not depend on which block finishes last.  The block that
 // completes the last chunk overall (counter done[0]) advances the step
 // counter.  Every counter is returned to zero for the next launch (no memset
@@ -1573,8 +1573,12 @@ __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ par
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] += val[u][v];
   const double c = block_sum_fixed<NV>(acc, sh, S1);
-  if ((int)threadIdx.x < S1) chunk_part[(int64_t)blockIdx.x * S1 + threadIdx.x] = c;
-  __threadfence();
+  if (threadIdx.x < 64) {
+    // the writers (S1 <= 9 threads) are all in wave 0, which alone needs the
+    // device-scope fence before thread 0 signals completion
+    if ((int)threadIdx.x < S1) chunk_part[(int64_t)blockIdx.x * S1 + threadIdx.x] = c;
+    __threadfence();
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     // realisation of this chunk: last r with chunk_start[r] <= blockIdx.x
@@ -1588,22 +1592,28 @@ __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ par
     last_r = atomicAdd(&done[1 + lo], 1u) == nch - 1 ? lo : -1;
   }
   __syncthreads();
-  const int r = last_r;  // the same in every thread of the block
-  if (r >= 0) {
+  const int r = last_r;
+  if (r >= 0 && threadIdx.x < 64) {
     __threadfence();
+    const int lane = threadIdx.x;
     const int c0 = chunk_start[r], c1 = chunk_start[r + 1];
     double a[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) a[v] = 0.0;
-    for (int k = c0 + (int)threadIdx.x; k < c1; k += kBlock) {
+    for (int k = c0 + lane; k < c1; k += 64) {
 #pragma unroll
       for (int v = 0; v < NV; ++v)
         if (v < S1)
           a[v] += __hip_atomic_load(&chunk_part[(int64_t)k * S1 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    const double tot = block_sum_fixed<NV>(a, sh, S1);
-    if ((int)threadIdx.x < S1) out[(int64_t)r * S1 + threadIdx.x] = tot;
-    if (threadIdx.x == 0) done[1 + r] = 0u;
+    constexpr int NK = halved_count(NV, 64);
+    constexpr int NB = halving_bits(NV, 64);
+    int ri = 0, rr = NV;
+    halve_sum<1, 64, NV, NV>(a, ri, rr, lane);
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+      if (k < rr && lane < (1 << NB) && ri + k < S1) out[(int64_t)r * S1 + ri + k] = a[k];
+    if (lane == 0) done[1 + r] = 0u;
   }
   if (threadIdx.x == 0 && atomicAdd(&done[0], 1u) == (uint32_t)(nchunks - 1)) {
     done[0] = 0u;
