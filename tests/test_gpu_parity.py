@@ -218,6 +218,10 @@ def test_walk3d_n8e6_one_step_sampled(prec):
     (xr, ref), = OS.steps(x, M, 1, w.D, w.dt, w.seed, (0, 0, 0), (1, 1, 1), prec == F32, rows=rows)
     assert np.abs(pos - xr).max() < (2e-6 if prec == F32 else 1e-12)
     assert normerr(got[:, rows], ref) < walk_tol(prec, w.D, w.dt)
+    # the binary64 audit of all eight species and of A - B over 8e6 particles
+    # (many reduction chunks in one realisation) against exactly rounded sums
+    ex = np.asarray(exact_sums(got))
+    assert np.all(np.abs(ens.audit()[0] - ex) <= 1e-12 * np.abs(ex[:8]).sum())
     # ordered pairs: n (n - 1) F(r) with the unit-cube pair-distance CDF
     # F(r) = 4 pi r^3 / 3 - 3 pi r^4 / 2 + 8 r^5 / 5 - r^6 / 6 (r <= 1)
     pairs, _ = ens.count_pairs(w.dt, w.D)
