@@ -87,11 +87,13 @@ class RwptError(RuntimeError):
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load librwpt.so (raises if it has not been built)."""
+def load_library(path: str | None = None):
+    """Load librwpt.so (raises if it has not been built); ``path`` defaults to
+    the module's LIB_PATH at call time."""
     global _lib
     if _lib is not None:
         return _lib
+    path = LIB_PATH if path is None else path
     if not os.path.exists(path):
         raise ImportError("librwpt.so is not built (%s); build it with python -m paper_1811_05474_amd._build" % path)
     lib = ctypes.CDLL(path)

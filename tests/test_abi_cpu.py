@@ -222,3 +222,20 @@ def test_init_refuses_more_particles_than_32_bit_indices(lib):
             assert ei.value.status == rwpt.RWPT_EINVAL and "too many particles" in str(ei.value)
     finally:
         rwpt.rwpt_destroy(ctx)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # no CPU fallback: without the built HIP library the binding refuses to run
+    import subprocess
+    import sys
+    code = ("from paper_1811_05474_amd import rwpt\n"
+            "rwpt.LIB_PATH = %r\n"
+            "try:\n"
+            "    rwpt.Ensemble(dim=2, n_species=2)\n"
+            "except ImportError as e:\n"
+            "    print('refused:', e)\n"
+            "else:\n"
+            "    raise SystemExit('ensemble created without the library')\n") % str(tmp_path / "librwpt.so")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "refused:" in r.stdout and "not built" in r.stdout
