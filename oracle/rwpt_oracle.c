@@ -42,7 +42,11 @@
  *   - normalisation: ROW is the literal P_ij = w_ij / sum_j w_ij.  SYM is the
  *     symmetric part (P + P^T)/2, i.e. P_ij = w_ij (1/r_i + 1/r_j)/2, which
  *     makes every pair exchange antisymmetric and conserves mass (the
- *     conservation requirement of Sec. 6).  SYM is the default.
+ *     conservation requirement of Sec. 6).  SYM is the default.  Which
+ *     form the paper means is parity unpinned: no printed value decides it.
+ *     Each form is pinned by its own mathematics (SYM: symmetric operator
+ *     with unit row and column sums, conserved totals; ROW: unit row sums;
+ *     both: the two-particle closed form).
  *   - cutoff predicate: a pair is a neighbour iff s^2 <= rc2 where
  *     rc2 = (kappa*kappa) * ((8*D)*dt) evaluated in binary64 and, for the
  *     binary32 predicate, rounded once to binary32; s^2 is evaluated in the
