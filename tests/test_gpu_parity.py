@@ -453,6 +453,56 @@ def test_non_unit_box():
     ens.close()
 
 
+def test_non_unit_box_3d():
+    n = 4000
+    lo, hi = (-1.0, 0.0, 2.0), (1.0, 0.5, 3.0)
+    x = f32(W.positions(n, 3, 33, lo, hi))
+    M = W.masses(n, 2, 33)
+    for lanes in (0, 4):
+        ens = make(dim=3, prec=F32, lanes=lanes, box_lo=lo, box_hi=hi)
+        ens.init([n], x, M)
+        ens.step(0.1, 1e-3, 2)
+        ref = oracle_run(x, M, 1e-3, 0.1, 2, 3.0, 32)
+        assert normerr(ens.masses(), ref) < 1e-5, lanes
+        ens.close()
+
+
+@pytest.mark.parametrize("prec", [F32, F64])
+@pytest.mark.parametrize("dim,kappa,lanes", [(1, 4.5, 0), (2, 2.0, 0), (2, 5.0, 4), (2, 5.0, 8),
+                                             (3, 2.5, 0), (3, 2.5, 4)])
+def test_other_cutoff_multiples(dim, kappa, lanes, prec):
+    # kappa sets the cutoff kappa * sigma (Sec. 2.2), hence the cell size and
+    # the stencils; masses after two steps follow the oracle at that kappa
+    n, dt = {1: 3000, 2: 4000, 3: 5000}[dim], 0.1
+    D = {1: 2e-4, 2: 3e-4, 3: 2e-3}[dim]
+    x = W.positions(n, dim, 40 + dim)
+    if prec == F32:
+        x = f32(x)
+    M = W.masses(n, 2, 40 + dim)
+    ens = make(dim=dim, prec=prec, kappa=kappa, lanes=lanes)
+    ens.init([n], x, M)
+    ens.step(dt, D, 2)
+    ref = oracle_run(x, M, D, dt, 2, kappa, 32 if prec == F32 else 64)
+    assert normerr(ens.masses(), ref) < (1e-5 if prec == F32 else 1e-12)
+    ens.close()
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_cutoff_wider_than_the_box(dim):
+    # kappa * sigma (3.8) exceeds the box diagonal: every pair interacts, so
+    # the sparse path gives the full matrix's result
+    n, D, dt = 1500, 2.0, 0.1
+    x = f32(W.positions(n, dim, 50 + dim))
+    M = W.masses(n, 2, 50 + dim)
+    ens = make(dim=dim, prec=F32)
+    ens.init([n], x, M)
+    ens.step(dt, D, 1)
+    assert ens.count_pairs(dt, D)[0] == n * (n - 1)
+    ref = oracle_run(x, M, D, dt, 1, math.inf, 32)
+    assert normerr(ens.masses(), ref) < 1e-5
+    ens.close()
+
+
 # --------------------------------------------------- determinism / resume ----
 
 def test_bitwise_deterministic_and_resumable():
