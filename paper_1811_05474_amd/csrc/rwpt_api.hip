@@ -90,7 +90,7 @@ struct rwpt_ctx {
   std::vector<StencilRow> h_st;
   std::vector<Tile> h_tiles;
   std::vector<int32_t> h_tile_start;
-  std::vector<int2> h_chunks;
+  std::vector<AuditChunk> h_chunks;
   std::vector<int32_t> h_chunk_start;
   int32_t ntiles = 0;
   int log2l = 3;
@@ -393,8 +393,10 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   c->h_chunk_start.assign(c->n_real + 1, 0);
   for (int r = 0; r < c->n_real; ++r) {
     c->h_chunk_start[r] = (int32_t)c->h_chunks.size();
-    for (int32_t t = c->h_tile_start[r]; t < c->h_tile_start[r + 1]; t += kAuditChunk)
-      c->h_chunks.push_back(make_int2(t, std::min<int32_t>(t + kAuditChunk, c->h_tile_start[r + 1])));
+    const int32_t t0 = c->h_tile_start[r], t1 = c->h_tile_start[r + 1];
+    const int32_t nch = (t1 - t0 + kAuditChunk - 1) / kAuditChunk;
+    for (int32_t t = t0; t < t1; t += kAuditChunk)
+      c->h_chunks.push_back(AuditChunk{t, std::min<int32_t>(t + kAuditChunk, t1), r, nch});
   }
   c->h_chunk_start[c->n_real] = (int32_t)c->h_chunks.size();
   if (cell_off >= (int64_t)1 << 31) return fail(c, RWPT_EUNSUPPORTED, "cell grid too large (%lld cells)", (long long)cell_off);
@@ -424,11 +426,11 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
     HIPCHK(c, c->bbox.ensure((size_t)(c->cap / kDenseColTile + 1) * 2 * c->dim * sizeof(float)));
     HIPCHK(c, c->bparts.ensure((size_t)3 * 16 * ncb * c->cap * sizeof(uint16_t)));
   }
-  HIPCHK(c, c->d_chunks.ensure(std::max<size_t>(1, c->h_chunks.size()) * sizeof(int2)));
+  HIPCHK(c, c->d_chunks.ensure(std::max<size_t>(1, c->h_chunks.size()) * sizeof(AuditChunk)));
   HIPCHK(c, c->d_chunk_start.ensure(c->h_chunk_start.size() * sizeof(int32_t)));
   HIPCHK(c, c->chunk_part.ensure(std::max<size_t>(1, c->h_chunks.size()) * (c->S + 1) * sizeof(double)));
   if (!c->h_chunks.empty())
-    HIPCHK(c, hipMemcpyAsync(c->d_chunks.p, c->h_chunks.data(), c->h_chunks.size() * sizeof(int2),
+    HIPCHK(c, hipMemcpyAsync(c->d_chunks.p, c->h_chunks.data(), c->h_chunks.size() * sizeof(AuditChunk),
                              hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_chunk_start.p, c->h_chunk_start.data(),
                            c->h_chunk_start.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
@@ -577,7 +579,7 @@ static rwpt_status enqueue_step(rwpt_ctx* c, bool sort, bool walk) {
   c->mcur ^= 1;
   {
     PhaseScope ps(c, PH_AUDIT);
-    HIPCHK(c, launch_audit_reduce(c->audit_part.as<double>(), c->S + 1, c->d_chunks.as<int2>(),
+    HIPCHK(c, launch_audit_reduce(c->audit_part.as<double>(), c->S + 1, c->d_chunks.as<AuditChunk>(),
                                   (int32_t)c->h_chunks.size(), c->chunk_part.as<double>(),
                                   c->d_chunk_start.as<int32_t>(), c->n_real, c->audit_out.as<double>(),
                                   c->audit_done.as<uint32_t>(), c->step_ctr.as<uint64_t>(), 1, c->stream));
@@ -765,9 +767,9 @@ rwpt_status rwpt_init_ensemble(rwpt_ctx* c, int32_t n_real, const int64_t* n_per
   HIPCHK(c, c->q.ensure(cap * ts));
   HIPCHK(c, c->d_real_start.ensure((n_real + 1) * sizeof(int64_t)));
   HIPCHK(c, c->audit_out.ensure((size_t)n_real * (S + 1) * sizeof(double)));
-  // completion counters of the audit kernel (one overall, one per realisation)
-  HIPCHK(c, c->audit_done.ensure((size_t)(n_real + 1) * sizeof(uint32_t)));
-  HIPCHK(c, hipMemsetAsync(c->audit_done.p, 0, (size_t)(n_real + 1) * sizeof(uint32_t), c->stream));
+  // completion counters of the audit kernel (one per realisation)
+  HIPCHK(c, c->audit_done.ensure((size_t)n_real * sizeof(uint32_t)));
+  HIPCHK(c, hipMemsetAsync(c->audit_done.p, 0, (size_t)n_real * sizeof(uint32_t), c->stream));
 
   // host staging: particle-major in the path's precision
   std::vector<unsigned char> hp(PS * cap * ts, 0), hm(Sa * cap * ts, 0);

@@ -76,13 +76,20 @@ hipError_t launch_nbr_fill(int fp64, int dim, int log2l, const PairArgs& a, hipS
 
 // Per-realisation FP64 reduction of the per-tile audit partials in two fixed-
 // order levels (chunks of at most kAuditChunk tiles inside one realisation,
-// then the chunks of each realisation) in one launch; `done` holds n_real + 1
+// then the chunks of each realisation) in one launch; `done` holds n_real
 // zeroed completion counters that the kernel returns to zero.  Optionally
 // advances the step counter.
-// Few, large chunks: every chunk block ends in a device-scope fence and
-// completion atomics on shared counters, which serialise across blocks.
+// Few, large chunks: every chunk block of a realisation with more than one
+// chunk ends in a device-scope fence and a completion atomic on a shared
+// counter, which serialise across blocks; a realisation of one chunk needs
+// neither.
 constexpr int kAuditChunk = 2048;
-hipError_t launch_audit_reduce(const double* part, int32_t S1, const int2* chunks, int32_t nchunks,
+struct AuditChunk {
+  int32_t begin, end;  // tiles [begin, end) of one realisation
+  int32_t real;        // that realisation
+  int32_t n_in_real;   // chunks of that realisation
+};
+hipError_t launch_audit_reduce(const double* part, int32_t S1, const AuditChunk* chunks, int32_t nchunks,
                                double* chunk_part, const int32_t* chunk_start, int32_t n_real,
                                double* out, uint32_t* done, uint64_t* step_ctr, int32_t bump,
                                hipStream_t s);

@@ -1536,34 +1536,35 @@ __device__ __forceinline__ double block_sum_fixed(double (&acc)[NV], double (*sh
 }
 
 // Audit in one launch: every block sums one chunk of at most kAuditChunk
-// consecutive tiles (never straddling realisations; each thread loads all of
-// its kAuditChunk / kBlock tiles at once) in a fixed order.  The block that
-// completes a realisation's last chunk (counter done[1 + r]) sums that
-// realisation's chunk partials in chunk order with one wave (lanes over
-// chunks, then recursive halving), so realisations are finalised in parallel and
-// the result does not depend on which block finishes last.  The block that
-// completes the last chunk overall (counter done[0]) advances the step
-// counter.  Every counter is returned to zero for the next launch (no memset
-// node, so the launch can be captured).
+// consecutive tiles of one realisation (each thread loads all of its
+// kAuditChunk / kBlock tiles at once) in a fixed order.  A realisation of one
+// chunk is finished by that block.  Otherwise each chunk block publishes its
+// sums, and the block that completes the realisation's last chunk (counter
+// done[r]) adds the realisation's chunk sums in chunk order with one wave
+// (lanes over chunks, then recursive halving), so realisations are finalised
+// in parallel and the result does not depend on which block finishes last.
+// Block 0 advances the step counter, which no block of this launch reads.
+// The counters are returned to zero for the next launch (no memset node, so
+// the launch can be captured).
 __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ part, int32_t S1,
-                                                  const int2* __restrict__ chunks, int32_t nchunks,
+                                                  const AuditChunk* __restrict__ chunks,
                                                   double* __restrict__ chunk_part,
-                                                  const int32_t* __restrict__ chunk_start, int32_t n_real,
+                                                  const int32_t* __restrict__ chunk_start,
                                                   double* __restrict__ out, uint32_t* __restrict__ done,
                                                   uint64_t* __restrict__ step_ctr, int32_t bump) {
   constexpr int NV = kAuditValues;
   __shared__ double sh[kBlock / 64][NV];
-  __shared__ int last_r;
-  const int2 ch = chunks[blockIdx.x];
+  __shared__ int last;
+  const AuditChunk ch = chunks[blockIdx.x];
   // every load of the thread's tiles first, then the sums in tile order
   constexpr int U = kAuditChunk / kBlock;
   double val[U][NV];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int t = ch.x + (int)threadIdx.x + u * kBlock;
+    const int t = ch.begin + (int)threadIdx.x + u * kBlock;
     const double* pt = part + (int64_t)t * S1;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) val[u][v] = (t < ch.y && v < S1) ? pt[v] : 0.0;
+    for (int v = 0; v < NV; ++v) val[u][v] = (t < ch.end && v < S1) ? pt[v] : 0.0;
   }
   double acc[NV];
 #pragma unroll
@@ -1573,6 +1574,12 @@ __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ par
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] += val[u][v];
   const double c = block_sum_fixed<NV>(acc, sh, S1);
+  if (bump && blockIdx.x == 0 && threadIdx.x == 0) *step_ctr = *step_ctr + 1;
+  const int r = ch.real;
+  if (ch.n_in_real == 1) {
+    if ((int)threadIdx.x < S1) out[(int64_t)r * S1 + threadIdx.x] = c;
+    return;
+  }
   if (threadIdx.x < 64) {
     // the writers (S1 <= 9 threads) are all in wave 0, which alone needs the
     // device-scope fence before thread 0 signals completion
@@ -1580,20 +1587,9 @@ __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ par
     __threadfence();
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // realisation of this chunk: last r with chunk_start[r] <= blockIdx.x
-    int lo = 0, hi = n_real - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (chunk_start[mid] <= (int)blockIdx.x) lo = mid;
-      else hi = mid - 1;
-    }
-    const uint32_t nch = (uint32_t)(chunk_start[lo + 1] - chunk_start[lo]);
-    last_r = atomicAdd(&done[1 + lo], 1u) == nch - 1 ? lo : -1;
-  }
+  if (threadIdx.x == 0) last = atomicAdd(&done[r], 1u) == (uint32_t)(ch.n_in_real - 1);
   __syncthreads();
-  const int r = last_r;
-  if (r >= 0 && threadIdx.x < 64) {
+  if (last && threadIdx.x < 64) {
     __threadfence();
     const int lane = threadIdx.x;
     const int c0 = chunk_start[r], c1 = chunk_start[r + 1];
@@ -1613,11 +1609,7 @@ __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ par
 #pragma unroll
     for (int k = 0; k < NK; ++k)
       if (k < rr && lane < (1 << NB) && ri + k < S1) out[(int64_t)r * S1 + ri + k] = a[k];
-    if (lane == 0) done[1 + r] = 0u;
-  }
-  if (threadIdx.x == 0 && atomicAdd(&done[0], 1u) == (uint32_t)(nchunks - 1)) {
-    done[0] = 0u;
-    if (bump) *step_ctr = *step_ctr + 1;
+    if (lane == 0) done[r] = 0u;
   }
 }
 
@@ -1885,14 +1877,14 @@ hipError_t launch_nbr_fill(int fp64, int dim, int log2l, const PairArgs& a, hipS
   });
 }
 
-hipError_t launch_audit_reduce(const double* part, int32_t S1, const int2* chunks, int32_t nchunks,
+hipError_t launch_audit_reduce(const double* part, int32_t S1, const AuditChunk* chunks, int32_t nchunks,
                                double* chunk_part, const int32_t* chunk_start, int32_t n_real,
                                double* out, uint32_t* done, uint64_t* step_ctr, int32_t bump,
                                hipStream_t s) {
   if (n_real <= 0 || nchunks <= 0) return hipSuccess;
   if (S1 < 1 || S1 > kAuditValues) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_audit, dim3((unsigned)nchunks), dim3(kBlock), 0, s, part, S1, chunks, nchunks,
-                     chunk_part, chunk_start, n_real, out, done, step_ctr, bump);
+  hipLaunchKernelGGL(k_audit, dim3((unsigned)nchunks), dim3(kBlock), 0, s, part, S1, chunks, chunk_part,
+                     chunk_start, out, done, step_ctr, bump);
   return hipGetLastError();
 }
 
