@@ -79,7 +79,7 @@ struct rwpt_ctx {
   DevBuf src_of;                         // previous sorted slot of each sorted particle
   int mcur = 0;                          // mass buffer holding the current masses (0: mass0, 1: mass1)
   DevBuf cell_count, cell_start, scan_part;
-  DevBuf d_rp, d_st, d_tiles, d_tile_start, d_real_start;
+  DevBuf d_rp, d_st, d_tiles, d_tile_start, d_real_start, d_blk_real;
   DevBuf audit_part, audit_out, step_ctr, counts, d_chunks, d_chunk_start, chunk_part, audit_done;
   DevBuf bbox, bparts;  // full-matrix path
   bool dense = false;   // full-matrix path selected at init
@@ -503,7 +503,8 @@ static rwpt_status enqueue_sort(rwpt_ctx* c, bool walk, bool move_mass) {
   {
     PhaseScope ps(c, PH_WALK_KEY);
     HIPCHK(c, launch_walk_key(fp64, c->dim, c->pos0.p, c->pos1.p, c->id.as<uint32_t>(), n,
-                              c->d_rp.as<RealParams>(), c->d_real_start.as<int64_t>(), c->n_real,
+                              c->d_rp.as<RealParams>(), c->d_real_start.as<int64_t>(),
+                              c->d_blk_real.as<int32_t>(), c->n_real,
                               c->step_ctr.as<uint64_t>(), c->cfg.seed, walk ? 1 : 0,
                               c->cell_count.as<uint32_t>(), c->key.as<uint32_t>(),
                               c->slot.as<uint32_t>(), c->stream));
@@ -817,6 +818,17 @@ rwpt_status rwpt_init_ensemble(rwpt_ctx* c, int32_t n_real, const int64_t* n_per
   HIPCHK(c, hipMemcpyAsync(c->mass0.p, hm.data(), hm.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->id.p, hid.data(), cap * 4, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_real_start.p, c->real_start.data(), (n_real + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, c->stream));
+  // realisation of the first particle of every block of the walk launch
+  // (realisations keep their sizes and stay contiguous through every sort)
+  const int64_t nblk = (N + kBlock - 1) / kBlock;
+  std::vector<int32_t> blk_real((size_t)std::max<int64_t>(1, nblk), 0);
+  for (int64_t b = 0, rr = 0; b < nblk; ++b) {
+    while (rr + 1 < n_real && c->real_start[rr + 1] <= b * kBlock) ++rr;
+    blk_real[b] = (int32_t)rr;
+  }
+  HIPCHK(c, c->d_blk_real.ensure(blk_real.size() * sizeof(int32_t)));
+  HIPCHK(c, hipMemcpyAsync(c->d_blk_real.p, blk_real.data(), blk_real.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemsetAsync(c->step_ctr.p, 0, sizeof(uint64_t), c->stream));
   HIPCHK(c, hipMemcpyAsync(c->audit_out.p, c->audit_init.data(), c->audit_init.size() * sizeof(double),
@@ -1405,7 +1417,7 @@ void rwpt_destroy(rwpt_ctx* c) {
     DevBuf* bufs[] = {&c->pos0, &c->pos1, &c->mass0, &c->mass1, &c->id, &c->key, &c->slot,
                       &c->tmp_src, &c->tmp_id, &c->tmp_key, &c->skey, &c->r, &c->q, &c->cell_count,
                       &c->cell_start, &c->scan_part, &c->d_rp, &c->d_st, &c->d_tiles,
-                      &c->d_tile_start, &c->d_real_start, &c->audit_part, &c->audit_out,
+                      &c->d_tile_start, &c->d_real_start, &c->d_blk_real, &c->audit_part, &c->audit_out,
                       &c->step_ctr, &c->counts, &c->d_chunks, &c->d_chunk_start, &c->chunk_part,
                       &c->audit_done, &c->bbox, &c->bparts, &c->nb_meta, &c->nb_idx, &c->nb_w,
                       &c->nb_src, &c->src_of};

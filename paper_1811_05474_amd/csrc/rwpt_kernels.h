@@ -24,10 +24,12 @@ constexpr int kScanChunk = kBlock * kScanItems;
 constexpr int64_t kScanDirectMax = 256;  // up to this many scan blocks (one partial per thread), no top-level scan launch
 
 // Random walk + reflection (optional) and cell key / in-cell slot of every particle.
-// pos_in/pos_out may not alias.
+// pos_in/pos_out may not alias.  blk_real[b] is the realisation of particle
+// b * kBlock (one entry per block of the launch).
 hipError_t launch_walk_key(int fp64, int dim, const void* pos_in, void* pos_out,
                            const uint32_t* id, int32_t n, const RealParams* rp,
-                           const int64_t* real_start, int32_t n_real, const uint64_t* step_ctr,
+                           const int64_t* real_start, const int32_t* blk_real, int32_t n_real,
+                           const uint64_t* step_ctr,
                            uint64_t seed, int32_t do_walk, uint32_t* cell_count, uint32_t* key,
                            uint32_t* slot, hipStream_t s);
 

@@ -168,17 +168,15 @@ template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_walk_key(
     const T* __restrict__ pos_in, T* __restrict__ pos_out,
     const uint32_t* __restrict__ id, int32_t n, const RealParams* __restrict__ rp,
-    const int64_t* __restrict__ real_start, int32_t n_real, const uint64_t* __restrict__ step_ctr,
-    uint64_t seed, int32_t do_walk, uint32_t* __restrict__ cell_count, uint32_t* __restrict__ key_out,
-    uint32_t* __restrict__ slot_out) {
+    const int64_t* __restrict__ real_start, const int32_t* __restrict__ blk_real, int32_t n_real,
+    const uint64_t* __restrict__ step_ctr, uint64_t seed, int32_t do_walk,
+    uint32_t* __restrict__ cell_count, uint32_t* __restrict__ key_out, uint32_t* __restrict__ slot_out) {
   const int p = blockIdx.x * kBlock + threadIdx.x;
   if (p >= n) return;
-  int lo = 0, hi = n_real - 1;  // last realisation whose first particle is <= p
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (real_start[mid] <= p) lo = mid;
-    else hi = mid - 1;
-  }
+  // last realisation whose first particle is <= p, from that of the block's
+  // first particle (one block rarely spans more than two realisations)
+  int lo = blk_real[blockIdx.x];
+  while (lo + 1 < n_real && real_start[lo + 1] <= p) ++lo;
   T x[DIM];
   load_pos<T, DIM>(pos_in, p, x);
   auto walk_and_key = [&](const RealParams& P) -> uint32_t {
@@ -1621,14 +1619,14 @@ static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1
 
 hipError_t launch_walk_key(int fp64, int dim, const void* pos_in, void* pos_out,
                            const uint32_t* id, int32_t n, const RealParams* rp,
-                           const int64_t* real_start, int32_t n_real, const uint64_t* step_ctr,
-                           uint64_t seed, int32_t do_walk, uint32_t* cell_count, uint32_t* key,
-                           uint32_t* slot, hipStream_t s) {
+                           const int64_t* real_start, const int32_t* blk_real, int32_t n_real,
+                           const uint64_t* step_ctr, uint64_t seed, int32_t do_walk, uint32_t* cell_count,
+                           uint32_t* key, uint32_t* slot, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const dim3 g(blocks_for(n)), b(kBlock);
 #define RWPT_WK(T, D)                                                                             \
   hipLaunchKernelGGL((k_walk_key<T, D>), g, b, 0, s, (const T*)pos_in, (T*)pos_out, id, n, rp, \
-                     real_start, n_real, step_ctr, seed, do_walk, cell_count, key, slot)
+                     real_start, blk_real, n_real, step_ctr, seed, do_walk, cell_count, key, slot)
   if (fp64) {
     if (dim == 1) RWPT_WK(double, 1);
     else if (dim == 2) RWPT_WK(double, 2);
