@@ -931,6 +931,27 @@ def test_graph_eager_split_and_interleaved_queries_agree_bitwise(lanes, rw, prec
         assert normerr(runs[0][0], ref) < (1e-5 if prec == F32 else 1e-12)
 
 
+def test_cell_grids_of_different_refinement_agree_over_steps():
+    """Ten FP64 steps with the walk on a grid of 11 k cells and on one of 44 k
+    cells give the same masses and positions (same neighbour sets, summation
+    order aside): the cell counts restart from zero every step."""
+    n, D, dt = 30000, 1e-4, 0.1
+    x = W.positions(n, 2, 78)
+    M = W.masses(n, 2, 78)
+    out = []
+    for refine in ((4.0, 2.0, 0.0), (16.0, 2.0, 0.0)):
+        ens = make(dim=2, prec=F64, rw=1.0, refine=refine, seed=78)
+        ens.init([n], x, M)
+        ens.step(dt, D, 10)
+        st = ens.stats()
+        out.append((st["n_cells"], ens.masses(), ens.positions(), ens.count_pairs(dt, D)[0]))
+        ens.close()
+    (cells_a, m_a, x_a, p_a), (cells_b, m_b, x_b, p_b) = out
+    assert 2 * cells_a < cells_b
+    assert np.array_equal(x_a, x_b) and p_a == p_b
+    assert normerr(m_a, m_b) < 1e-12
+
+
 def test_cell_scan_both_forms_agree():
     """Grids of more than 256 scan blocks (1.05e6 cells) take the three-launch
     cell scan, smaller ones the two-launch form: the same FP64 step on both
