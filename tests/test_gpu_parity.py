@@ -157,6 +157,31 @@ def test_neighbor_lists_bit_exact_2d(prec, lanes):
 
 
 @pytest.mark.parametrize("prec", [F32, F64])
+@pytest.mark.parametrize("dim,lanes", [(1, 0), (1, 16), (2, 0), (2, -1), (2, 8), (3, 0), (3, 4)])
+def test_lattice_pairs_exactly_at_the_cutoff(dim, lanes, prec):
+    # spacing h = 3/32 and kappa^2 8 D dt = 9 * 2^-10 = h^2, exact in binary32:
+    # axis neighbours sit exactly on the cutoff and are included, diagonal
+    # ones are not; the lists match the oracle's bit for bit
+    m = {1: 10, 2: 10, 3: 6}[dim]
+    idx = np.stack(np.meshgrid(*([np.arange(m)] * dim), indexing="ij"), -1).reshape(-1, dim)
+    x = (2.0 + 3.0 * idx) / 32.0
+    n = x.shape[0]
+    D, dt = 2.0 ** -10, 0.125
+    M = W.masses(n, 2, 7)
+    ens = make(dim=dim, prec=prec, lanes=lanes)
+    ens.init([n], x, M)
+    rp, cols = ens.neighbors(dt, D)
+    rp0, cols0 = oracle.neighbors(x, 3.0, D, dt, 32 if prec == F32 else 64)
+    assert np.array_equal(rp, rp0) and np.array_equal(cols, cols0)
+    expect = 1 + sum((idx[:, k] > 0).astype(int) + (idx[:, k] < m - 1).astype(int) for k in range(dim))
+    assert np.array_equal(np.diff(rp), expect)
+    ens.step(dt, D, 1)
+    ref = oracle_run(x, M, D, dt, 1, 3.0, 32 if prec == F32 else 64)
+    assert normerr(ens.masses(), ref) < (1e-5 if prec == F32 else 1e-12)
+    ens.close()
+
+
+@pytest.mark.parametrize("prec", [F32, F64])
 @pytest.mark.parametrize("lanes", [0, -1, 1, 4, 8, 16])
 def test_walk2d_step_with_walk_replayed(prec, lanes):
     n, D, dt, seed = 30000, 2e-4, 0.1, 99

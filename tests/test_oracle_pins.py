@@ -54,6 +54,22 @@ def test_two_particles_at_one_sigma(norm, d):
     assert np.allclose(out[:, 1], exp1, rtol=1e-14, atol=0)
 
 
+@pytest.mark.parametrize("dim,m", [(1, 10), (2, 10), (3, 6)])
+@pytest.mark.parametrize("prec", [32, 64])
+def test_lattice_neighbours_exactly_at_the_cutoff(dim, m, prec):
+    # Lattice spacing h = 3/32 with 8 D dt = 2^-10, so kappa^2 8 D dt = h^2
+    # exactly in binary32 and binary64: axis neighbours sit exactly on the
+    # cutoff and count ("within" s_max, Sec. 2.1), diagonal ones (2 h^2) do not.
+    idx = np.stack(np.meshgrid(*([np.arange(m)] * dim), indexing="ij"), -1).reshape(-1, dim)
+    x = (2.0 + 3.0 * idx) / 32.0
+    rp, cols = oracle.neighbors(x, 3.0, 2.0 ** -10, 0.125, prec)
+    expect = 1 + sum((idx[:, k] > 0).astype(int) + (idx[:, k] < m - 1).astype(int) for k in range(dim))
+    assert np.array_equal(np.diff(rp), expect)
+    for i in (0, len(x) // 2):
+        nb = cols[rp[i]:rp[i + 1]]
+        assert np.all(np.abs(idx[nb] - idx[i]).sum(axis=1) <= 1)
+
+
 def test_two_particles_at_cutoff_edge():
     # At s = 3 sigma the weight is e^-9 (Sec. 2.2: the pad captures the
     # density out to 3 sigma); just beyond, the pair does not interact.
