@@ -69,6 +69,8 @@ def _load():
         lib.orc_walk_adv.restype = i32
         lib.orc_neighbors.argtypes = [i64, i32, vp, f64, f64, f64, i32, vp, vp, i64]
         lib.orc_neighbors.restype = i64
+        lib.orc_neighbors_rows.argtypes = [i64, i32, vp, f64, f64, f64, i32, vp, i64, vp, vp, i64]
+        lib.orc_neighbors_rows.restype = i64
         lib.orc_transfer_rows.argtypes = [i64, i32, i32, vp, vp, vp, f64, f64, f64, i32, i32, i32,
                                           i32, vp, i64, vp]
         lib.orc_transfer_rows.restype = i32
@@ -138,20 +140,27 @@ def walk(x: np.ndarray, ids: np.ndarray, seed: int, step: int, D_rw: float, dt: 
     return x
 
 
-def neighbors(x: np.ndarray, kappa: float, D: float, dt: float, prec: int = 32):
+def neighbors(x: np.ndarray, kappa: float, D: float, dt: float, prec: int = 32, rows=None):
     """Neighbour lists within s_max = kappa*sqrt(8 D dt) (Sec. 2.1/2.2), j = i included.
 
-    Returns (rowptr int64[n+1], cols int32[nnz]) with ascending columns."""
+    Returns (rowptr int64[m+1], cols int32[nnz]) with ascending columns, for
+    every particle (m = n) or, with ``rows``, for those particles in that
+    order (m = len(rows))."""
     x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
     n, d = x.shape
     lib = _load()
-    total = lib.orc_neighbors(n, d, _ptr(x), float(kappa), float(D), float(dt), int(prec), None, None, -1)
+    if rows is not None:
+        rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64).reshape(-1))
+        rows_p, m = _ptr(rows), rows.size
+    else:
+        rows_p, m = None, n
+    args = (n, d, _ptr(x), float(kappa), float(D), float(dt), int(prec), rows_p, m if rows is not None else 0)
+    total = lib.orc_neighbors_rows(*args, None, None, -1)
     if total < 0:
         raise ValueError("orc_neighbors failed (%d)" % total)
-    rowptr = np.zeros(n + 1, dtype=np.int64)
+    rowptr = np.zeros(m + 1, dtype=np.int64)
     cols = np.zeros(max(int(total), 1), dtype=np.int32)
-    got = lib.orc_neighbors(n, d, _ptr(x), float(kappa), float(D), float(dt), int(prec), _ptr(rowptr),
-                            _ptr(cols), int(total))
+    got = lib.orc_neighbors_rows(*args, _ptr(rowptr), _ptr(cols), int(total))
     assert got == total
     return rowptr, cols[:total]
 
@@ -172,7 +181,7 @@ def transfer(x: np.ndarray, M: np.ndarray, D: float, dt: float, kappa: float = 3
     assert M.shape == (S, n)
     ra, rb = (-1, -1) if react is None else react
     if rows is not None:
-        rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        rows = np.ascontiguousarray(np.asarray(rows, dtype=np.int64).reshape(-1))
         out = np.zeros((S, rows.size), dtype=np.float64)
         rows_p, nrows = _ptr(rows), rows.size
     else:

@@ -389,9 +389,18 @@ static int cmp_i32(const void *a, const void *b) {
   return (x > y) - (x < y);
 }
 
-int64_t orc_neighbors(int64_t n, int d, const double *x, double kappa, double D, double dt,
-                      int prec, int64_t *rowptr, int32_t *cols, int64_t cap) {
+/* rows/nrows: when rows != NULL only those rows are listed, in the given
+ * order (rowptr then has nrows + 1 entries); every entry must lie in [0, n). */
+int64_t orc_neighbors_rows(int64_t n, int d, const double *x, double kappa, double D, double dt,
+                           int prec, const int64_t *rows, int64_t nrows, int64_t *rowptr,
+                           int32_t *cols, int64_t cap) {
   if (n < 0 || d < 1 || d > 3 || D <= 0 || dt <= 0 || !(kappa > 0)) return ORC_EINVAL;
+  if (rows) {
+    if (nrows < 0) return ORC_EINVAL;
+    for (int64_t t = 0; t < nrows; ++t)
+      if (rows[t] < 0 || rows[t] >= n) return ORC_EINVAL;
+  }
+  const int64_t nout = rows ? nrows : n;
   int full = isinf(kappa);
   double rc2 = cutoff_rc2(kappa, D, dt);
   float rc2f = (float)rc2;
@@ -405,7 +414,8 @@ int64_t orc_neighbors(int64_t n, int d, const double *x, double kappa, double D,
     return ORC_ENOMEM;
   }
   if (rowptr && cap >= 0) rowptr[0] = 0;
-  for (int64_t i = 0; i < n; ++i) {
+  for (int64_t t = 0; t < nout; ++t) {
+    const int64_t i = rows ? rows[t] : t;
     nbr_ctx c = {x, d, rc2, rc2f, prec, full, 0, row, n};
     if (use_grid) grid_visit(&g, x, i, nbr_visit, &c);
     else
@@ -413,11 +423,16 @@ int64_t orc_neighbors(int64_t n, int d, const double *x, double kappa, double D,
     qsort(row, (size_t)c.count, sizeof(int32_t), cmp_i32);
     if (cols && total + c.count <= cap) memcpy(cols + total, row, (size_t)c.count * sizeof(int32_t));
     total += c.count;
-    if (rowptr && cap >= 0) rowptr[i + 1] = total;
+    if (rowptr && cap >= 0) rowptr[t + 1] = total;
   }
   free(row);
   if (use_grid) grid_free(&g);
   return total;
+}
+
+int64_t orc_neighbors(int64_t n, int d, const double *x, double kappa, double D, double dt,
+                      int prec, int64_t *rowptr, int32_t *cols, int64_t cap) {
+  return orc_neighbors_rows(n, d, x, kappa, D, dt, prec, NULL, 0, rowptr, cols, cap);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -488,8 +503,9 @@ static void dm_visit(int64_t i, int64_t j, void *vctx) {
  *   norm:  0 = SYM, 1 = ROW
  *   prec:  32 or 64 -- precision of the cutoff predicate only
  *   react_a/react_b: species pair of A + B -> 0, or -1 to disable
- *   rows/nrows: when rows != NULL only those rows are computed and M_out is
- *          then nrows*S... laid out as M_out[s*nrows + t]
+ *   rows/nrows: when rows != NULL only those rows are computed, in the given
+ *          order (repeats allowed), and M_out is S*nrows laid out as
+ *          M_out[s*nrows + t]; every entry must lie in [0, n), else ORC_EINVAL
  *   r_out: optional n row sums
  */
 int orc_transfer_rows(int64_t n, int d, int S, const double *x, const double *M_in, double *M_out,
@@ -502,6 +518,11 @@ int orc_transfer_rows(int64_t n, int d, int S, const double *x, const double *M_
   if ((react_a >= 0) != (react_b >= 0) || react_a >= S || react_b >= S ||
       (react_a >= 0 && react_a == react_b))
     return ORC_EINVAL;
+  if (rows) {
+    if (nrows < 0) return ORC_EINVAL;
+    for (int64_t t = 0; t < nrows; ++t)
+      if (rows[t] < 0 || rows[t] >= n) return ORC_EINVAL;
+  }
   int64_t nout = rows ? nrows : n;
   double *dM = (double *)calloc((size_t)(nout > 0 ? nout : 1) * (size_t)S, sizeof(double));
   double *r = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));

@@ -452,3 +452,56 @@ def test_cutoff_gap_is_bounded_by_the_neglected_kernel_mass(d):
     gap = np.abs(sparse - dense).max() / np.abs(M).max()
     tail = {1: erfc(3.0), 2: math.exp(-9.0), 3: erfc(3.0) + 6.0 / math.sqrt(math.pi) * math.exp(-9.0)}[d]
     assert tail / 1000 < gap < tail
+
+
+# ------------------------------------------------- row-subset modes ----------
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("kappa", [3.0, math.inf])
+@pytest.mark.parametrize("norm", [oracle.NORM_SYM, oracle.NORM_ROW])
+@pytest.mark.parametrize("react", [(0, 1), None])
+def test_transfer_row_subset_equals_the_full_output(d, kappa, norm, react):
+    # The explicit transfer of Eqs. (3)-(6) computes every particle's new
+    # masses from the same beginning-of-step state, so asking for a subset of
+    # rows (in any order, with repeats) must give exactly those columns of the
+    # full output, bit for bit; the row sums stay those of all particles.
+    n, S = {1: 700, 2: 900, 3: 800}[d], 3
+    D, dt = {1: 2e-4, 2: 1e-3, 3: 4e-3}[d], 0.1
+    x = f32(W.positions(n, d, 90 + d))
+    M = W.masses(n, S, 90 + d)
+    full, r_full = oracle.transfer(x, M, D, dt, kappa=kappa, norm=norm, prec=32, react=react, return_r=True)
+    rng = np.random.default_rng(91 + d)
+    rows = np.concatenate([rng.choice(n, 60, replace=False)[::-1], [n - 1, 0, 5, 5, n - 1]])
+    sub, r_sub = oracle.transfer(x, M, D, dt, kappa=kappa, norm=norm, prec=32, react=react, rows=rows,
+                                 return_r=True)
+    assert sub.shape == (S, rows.size)
+    assert np.array_equal(sub, full[:, rows])
+    assert np.array_equal(r_sub, r_full)
+    # an index slip would move a value to another column: every column differs
+    assert len({tuple(full[:, i]) for i in range(n)}) == n
+
+
+def test_transfer_row_subset_rejects_rows_outside_the_ensemble():
+    x = W.positions(50, 2, 1)
+    M = W.masses(50, 2, 1)
+    for bad in ([0, 50], [-1], [3, 7, 1 << 40]):
+        with pytest.raises(ValueError):
+            oracle.transfer(x, M, 1e-3, 0.1, rows=np.array(bad))
+    with pytest.raises(ValueError):
+        oracle.neighbors(x, 3.0, 1e-3, 0.1, rows=np.array([0, 50]))
+    assert oracle.transfer(x, M, 1e-3, 0.1, rows=np.array([], dtype=np.int64)).shape == (2, 0)
+
+
+@pytest.mark.parametrize("d,prec", [(1, 32), (2, 32), (2, 64), (3, 32)])
+def test_neighbor_row_subset_equals_the_full_lists(d, prec):
+    # the row-subset export lists exactly the full lists' rows, in the order asked
+    n = {1: 3000, 2: 4000, 3: 4000}[d]
+    D, dt = {1: 1e-4, 2: 5e-4, 3: 3e-3}[d], 0.1
+    x = f32(W.positions(n, d, 70 + d))
+    rp, cols = oracle.neighbors(x, 3.0, D, dt, prec)
+    rows = np.random.default_rng(d).choice(n, 300, replace=False)
+    rows = np.concatenate([rows, rows[:7]])
+    rp_s, cols_s = oracle.neighbors(x, 3.0, D, dt, prec, rows=rows)
+    assert rp_s.size == rows.size + 1
+    for t, i in enumerate(rows):
+        assert np.array_equal(cols_s[rp_s[t]:rp_s[t + 1]], cols[rp[i]:rp[i + 1]])
