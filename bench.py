@@ -52,17 +52,17 @@ PEAK_HBM_GBPS = 8000.0
 
 
 def exchange_flops_per_pair(dim: int, S: int) -> int:
-    """Algorithmic flops of the exchange pass per ordered in-cutoff pair (j != i):
-    dim differences, dim squares + (dim-1) adds, one exponent scale, one exp,
-    q_i + q_j, its product with w, and per species a difference, a product and
-    an accumulation."""
-    return dim + dim + (dim - 1) + 1 + 1 + 1 + 1 + 3 * S
+    """Algorithmic flops per ordered in-cutoff pair (j != i): one exp, 2 dim
+    for the separation (a difference and a square per axis), about 3 for the
+    weight's scale, its normalisation factor and its accumulation, and 2 per
+    species (a difference and a multiply-accumulate): 1 + 2 dim + 3 + 2 S."""
+    return 1 + 2 * dim + 3 + 2 * S
 
 
 def exchange_bytes_per_particle(dim: int, S: int, tsize: int) -> int:
-    """Algorithmic HBM bytes of the exchange pass per particle: read the
-    position, q and S masses, write S masses."""
-    return tsize * (dim + 1 + S) + tsize * S
+    """Algorithmic HBM bytes of the transfer per particle: read the position
+    and the S masses, write the S masses (tsize (dim + 2 S))."""
+    return tsize * (dim + 2 * S)
 
 
 def step_bytes_per_particle(dim: int, S: int, tsize: int) -> int:
@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--tile-lanes", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the batch workload in the default tiling instead of the autotuned one")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the comparison with the oracle")
     ap.add_argument("--workload", default=WORKLOAD,
                     help="workload name (default %s)" % WORKLOAD)
     return ap.parse_args()
@@ -132,11 +135,18 @@ def host_io(rwpt, W, w, precision, tile_lanes, repeats=3):
     return {"init_ms": best[0], "first_step_ms": best[1], "query_ms": best[2], "total_ms": sum(best)}
 
 
-def run_path(rwpt, W, w, precision, steps, warmup, tile_lanes, profile=True):
+def run_path(rwpt, W, w, precision, steps, warmup, tile_lanes, profile=True, autotune=False):
     import torch
 
     ens = ensemble_for(rwpt, w, precision, tile_lanes)
     init_ensemble(ens, W, w)
+    tuned_s = None
+    if autotune:
+        # outside the timed region: every candidate tiling is timed on a
+        # snapshot of the state, which is then restored
+        t0 = time.perf_counter()
+        rwpt.rwpt_autotune(ens.ctx, w.dt, w.D, 3)
+        tuned_s = time.perf_counter() - t0
     audit0 = ens.audit().sum(axis=0).tolist()
     ens.step(w.dt, w.D, warmup)
     ens.sync()
@@ -170,6 +180,7 @@ def run_path(rwpt, W, w, precision, steps, warmup, tile_lanes, profile=True):
                              "us_avg": (1e3 * v[0] / v[1]) if v[1] else 0.0} for k, v in prof.items() if v[1]}
     out["audit"] = ens.audit().sum(axis=0).tolist()
     out["tiling"] = rwpt.rwpt_get_tiling(ens.ctx)
+    out["autotune_s"] = tuned_s
     if profile and precision == rwpt.RWPT_FP32 and out["tiling"][0] == 4 and "rowsum" in out.get("phases", {}):
         # attainable rates of the row-broadcast kernels' inner loops on this
         # device, from register-only kernels running the same per-candidate code
@@ -178,6 +189,119 @@ def run_path(rwpt, W, w, precision, steps, warmup, tile_lanes, profile=True):
             ("rowsum", rwpt.RWPT_PROBE_ROWSUM), ("exchange", rwpt.RWPT_PROBE_EXCHANGE))}
     ens.close()
     return out
+
+
+def accuracy(rwpt, W, w, precision, tile_lanes, n_rows=2000):
+    """Error of one step of the path against the oracle, normwise over sampled
+    particles (max |dM| / max |M|), in two forms:
+
+    * identical positions: the walk switched off, so both sides transfer on
+      the seeded positions (binary32-rounded for the FP32 path): the bar is
+      1e-5 (FP32) or 1e-12 (FP64);
+    * with the walk: the oracle's own walk then its transfer, against the
+      path's walked step; positions may differ by an ulp, so the bar adds
+      0.3 * 2 kappa * 2 u / sigma (u the ulp of the box's largest coordinate).
+
+    Realisations: the first and, for a batch, the largest.  The full-matrix
+    workload is compared with the oracle at kappa = 7, which equals the full
+    matrix to e^-49 of the kernel."""
+    import oracle
+
+    f32 = precision == rwpt.RWPT_FP32
+    p = 32 if f32 else 64
+    bar = 1e-5 if f32 else 1e-12
+    x, M, sizes, Ds = W.make_inputs(w)
+    if f32:
+        x = x.astype(np.float32).astype(np.float64)
+        M = M.astype(np.float32).astype(np.float64)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    reals = sorted({0, int(np.argmax(sizes))})
+    kappa = w.kappa if math.isfinite(w.kappa) else 7.0
+    d_scale = Ds / w.D if w.D > 0 else None
+    rng = np.random.default_rng(12)
+    xmax = max(abs(v) for v in list(w.box_lo[:w.dim]) + list(w.box_hi[:w.dim]))
+    u = float(np.spacing(np.float32(xmax))) if f32 else float(np.spacing(np.float64(xmax)))
+    out = {}
+    for form, rw in (("identical_positions", 0.0), ("with_walk", w.rw_ratio)):
+        ens = rwpt.Ensemble(dim=w.dim, n_species=w.n_species, react=w.react, kappa=w.kappa, rw_ratio=rw,
+                            precision=precision, seed=w.seed, tile_lanes=tile_lanes, box_lo=w.box_lo,
+                            box_hi=w.box_hi, velocity=w.velocity if rw > 0 else (0.0, 0.0, 0.0),
+                            alpha_l=w.alpha_l, alpha_t=w.alpha_t)
+        ens.init(sizes, x, M, d_scale=d_scale)
+        ens.step(w.dt, w.D, 1)
+        got = ens.masses()
+        ens.close()
+        err, allow = 0.0, 0.0
+        for r in reals:
+            b, e = int(off[r]), int(off[r + 1])
+            rows = rng.choice(e - b, min(n_rows, e - b), replace=False)
+            Dr = float(Ds[r])
+            xr = x[b:e]
+            if rw > 0.0:
+                xr = oracle.walk(xr, np.arange(b, e, dtype=np.uint32), w.seed, 0, rw * Dr, w.dt, w.box_lo,
+                                 w.box_hi, velocity=w.velocity if any(w.velocity) else None,
+                                 alpha_l=w.alpha_l, alpha_t=w.alpha_t)
+                if f32:
+                    xr = xr.astype(np.float32).astype(np.float64)
+                allow = max(allow, 0.3 * 2.0 * kappa * 2.0 * u / math.sqrt(8.0 * Dr * w.dt))
+            ref = oracle.transfer(xr, M[:, b:e], Dr, w.dt, kappa=kappa, prec=p, react=w.react, rows=rows)
+            g = got[:, b + rows]
+            err = max(err, float(np.abs(g - ref).max() / np.abs(ref).max()))
+        out[form] = {"normwise_err": err, "bar": bar + allow, "within_bar": err < bar + allow}
+    out["scope"] = ("one step from the seeded state, %d sampled particles of realisation(s) %s, max |dM| / max |M| "
+                    "against the oracle (FP64 weights, cutoff predicate in the path's precision)"
+                    % (n_rows, reals))
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_single_thread(W, w, budget_cells=16):
+    """The oracle on one thread over a bounded sample: the particles of one
+    strip of the box (1/budget_cells of the first axis, same density and
+    neighbourhoods, the strip's own edges aside), one full step (walk +
+    transfer + reaction); pairs from the oracle's neighbour count of the
+    stepped sample."""
+    import oracle
+
+    x, M, sizes, Ds = W.make_inputs(w)
+    x = x.astype(np.float32).astype(np.float64)
+    b, e = 0, int(sizes[0])
+    lo, hi = w.box_lo[0], w.box_hi[0]
+    sel = np.flatnonzero(x[b:e, 0] < lo + (hi - lo) / budget_cells)
+    xs, Ms = x[b:e][sel], M[:, b:e][:, sel]
+    Dr = float(Ds[0])
+    kappa = w.kappa if math.isfinite(w.kappa) else 7.0
+    saved = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        if w.rw_ratio > 0 or any(w.velocity):
+            xs = oracle.walk(xs, sel.astype(np.uint32), w.seed, 0, w.rw_ratio * Dr, w.dt, w.box_lo, w.box_hi,
+                             velocity=w.velocity if any(w.velocity) else None, alpha_l=w.alpha_l,
+                             alpha_t=w.alpha_t)
+        oracle.transfer(xs, Ms, Dr, w.dt, kappa=kappa, prec=32, react=w.react)
+        dt_s = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(saved)
+    rp, _ = oracle.neighbors(xs.astype(np.float32).astype(np.float64), kappa, Dr, w.dt, 32)
+    unordered = 0.5 * (rp[-1] - sel.size)
+    return {
+        "value": unordered / dt_s,
+        "unit": "pair-interactions/s",
+        "cores": 1,
+        "sample": "one full step (walk + transfer + reaction, FP64 weights) of the %d particles in the first "
+                  "1/%d of the box along x (%d unordered pairs) on one thread: %.3f s"
+                  % (sel.size, budget_cells, int(unordered), dt_s),
+    }
 
 
 def cpu_baseline(W, w, unordered_pairs_per_step, budget_s=15.0):
@@ -224,6 +348,9 @@ def cpu_baseline(W, w, unordered_pairs_per_step, budget_s=15.0):
         "kind": "oracle",
         "sample": "%s of workload %s on %d OpenMP threads: %.3f s" % (sample, w.name, threads, dt_s),
         "steps_per_s": frac / dt_s,
+        "cpu_model": cpu_model(),
+        "host_cpus": os.cpu_count(),
+        "single_thread": cpu_single_thread(W, w) if w.n_real == 1 else None,
     }
 
 
@@ -286,15 +413,17 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # the batch of uneven realisations is timed in the tiling the autotuner picks
+    autotune = w.name == "batch2d_64" and args.tile_lanes == 0 and not args.no_autotune
     r32 = run_path(rwpt, W, w, rwpt.RWPT_FP32, args.steps, args.warmup, args.tile_lanes,
-                   profile=not args.profile_only)
+                   profile=not args.profile_only, autotune=autotune)
     if args.profile_only:
         print(json.dumps({"profile_only": True, "ms_per_step": r32["ms_per_step"]}))
         return
     hio = host_io(rwpt, W, w, rwpt.RWPT_FP32, args.tile_lanes)
     r64 = None
     if not args.no_fp64:
-        r64 = run_path(rwpt, W, w, rwpt.RWPT_FP64, args.steps, args.warmup, args.tile_lanes)
+        r64 = run_path(rwpt, W, w, rwpt.RWPT_FP64, args.steps, args.warmup, args.tile_lanes, autotune=autotune)
 
     unordered = 0.5 * r32["ordered_pairs_per_step"]
     steps_per_s = 1e3 / r32["ms_per_step"]
@@ -388,6 +517,8 @@ def main():
             "norm": "sym", "reaction": "A+B->0" if w.react else "none",
             "path": "dense" if dense else "sparse",
             "tile_lanes": r32["tiling"][0], "cell_refine": r32["tiling"][1],
+            "tiling_chosen_by": "rwpt_autotune (%.1f s, outside the timed region)" % r32["autotune_s"]
+            if r32["autotune_s"] is not None else "default",
             "unordered_pairs_per_step": unordered,
             "candidate_evaluations_per_step": r32["evaluations_per_step"],
         },
@@ -400,6 +531,10 @@ def main():
                                    "masses copied back",
                         pair_interactions_per_s=unordered / (hio["total_ms"] * 1e-3)),
     }
+    acc32 = acc64 = None
+    if not args.no_accuracy:
+        acc32 = accuracy(rwpt, W, w, rwpt.RWPT_FP32, r32["tiling"][0] if autotune else args.tile_lanes)
+        line["err_vs_oracle_fp32"] = acc32
     if r64 is not None:
         m32, m64 = r32["masses"], r64["masses"]
         line["fp64"] = {
@@ -407,9 +542,19 @@ def main():
             "steps_per_s": 1e3 / r64["ms_per_step"],
             "value": 0.5 * r64["ordered_pairs_per_step"] * 1e3 / r64["ms_per_step"],
             "phases_us": {k: round(v["us_avg"], 2) for k, v in r64["phases"].items()},
-            "fp32_speedup": r64["ms_per_step"] / r32["ms_per_step"],
-            "fp32_vs_fp64_normwise_mass_diff": float(np.abs(m32 - m64).max() / np.abs(m64).max()),
+            "fp32_vs_fp64_normwise_mass_diff_after_run": float(np.abs(m32 - m64).max() / np.abs(m64).max()),
         }
+        if not args.no_accuracy:
+            acc64 = accuracy(rwpt, W, w, rwpt.RWPT_FP64, r64["tiling"][0] if autotune else args.tile_lanes)
+            line["err_vs_oracle_fp64"] = acc64
+        # FP32 over FP64 speedup, stated only where both paths meet their bars
+        # against the oracle ("equal accuracy")
+        equal = (acc32 is not None and acc64 is not None and
+                 all(a[f]["within_bar"] for a in (acc32, acc64) for f in ("identical_positions", "with_walk")))
+        line["fp64"]["fp32_speedup"] = r64["ms_per_step"] / r32["ms_per_step"] if equal else None
+        line["fp64"]["fp32_speedup_at"] = ("equal accuracy: both paths within their bars against the oracle "
+                                           "(FP32 1e-5, FP64 1e-12, plus the walk allowance)" if equal else
+                                           "not stated: accuracy not established")
         for tag, r in (("fp32", r32), ("fp64", r64)):
             a0, a1 = r["audit0"], r["audit"]
             if w.react:

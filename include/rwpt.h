@@ -172,11 +172,27 @@ rwpt_status rwpt_count_pairs(rwpt_ctx *ctx, double dt, double D, int64_t *pairs_
 
 /* Debug export of the neighbour lists for the cutoff of (dt, D) and the
  * current positions, as CSR over the caller's particle order with ascending
- * global column indices, j = i included.  Call with cols == NULL to get the
+ * global column indices, j = i included.  The candidates are enumerated as
+ * the step's pair kernels enumerate them for the tiling in use (the chunked
+ * candidate rows of the binary32 four-lane tiles, whole or split; each
+ * particle's own cutoff box for one lane per particle; the stencil rows of
+ * the other tilings), each decided by the same cutoff predicate.  Call with cols == NULL to get the
  * number of entries in *nnz_out; then with rowptr (N + 1 int64) and cols
  * (*nnz_out int32) allocated.  Synchronous; does not change the state. */
 rwpt_status rwpt_neighbors(rwpt_ctx *ctx, double dt, double D, int64_t *rowptr, int32_t *cols,
                            int64_t *nnz_out);
+
+/* Debug: the row sums r_i = sum_j w_ij of the normalisation (Sec. 1.1, after
+ * Eq. 3) for the current positions and the cutoff of (dt, D), computed by the
+ * row-sum kernel of the sparse path in the launch shape a step uses (same
+ * tiling, candidate enumeration and cutoff predicate), returned in the
+ * caller's particle order (r_out: N doubles, host).  unit_weights = 1 replaces
+ * every weight by exp(0) = 1, so r_out[i] is exactly the number of particles
+ * j (j = i included) that the step's own kernel takes as neighbours of i.
+ * Synchronous; masses, positions and the step counter are unchanged.
+ * Errors: RWPT_EINVAL (bad dt, D, unit_weights or NULL r_out), RWPT_ESTATE
+ * (before init), RWPT_EUNSUPPORTED (full-matrix path), RWPT_EDEVICE. */
+rwpt_status rwpt_debug_rowsums(rwpt_ctx *ctx, double dt, double D, int32_t unit_weights, double *r_out);
 
 /* Per-phase timing.  While enabled, rwpt_step launches eagerly (no graph) and
  * brackets each kernel phase with HIP events on the context's stream.
@@ -202,7 +218,7 @@ typedef struct rwpt_stats_t {
   int64_t ordered_pairs;      /* pairs j != i within the cutoff */
   int64_t candidate_evals;    /* candidate evaluations of the sparse kernels */
   int32_t n_phases;           /* entries of phase_ms / phase_launches in use (<= 16) */
-  int32_t pad;
+  int32_t graph_captures;     /* step graphs captured since rwpt_create (use_graph = 1) */
   double phase_ms[16];        /* per-phase milliseconds since the last profile reset */
   int64_t phase_launches[16];
 } rwpt_stats_t;

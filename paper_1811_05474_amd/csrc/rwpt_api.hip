@@ -104,6 +104,7 @@ struct rwpt_ctx {
 
   // captured steps: [2 * (sort ? 0 : 1) + mcur at the start of the step]
   hipGraphExec_t gx[4] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t n_captures = 0;  // step graphs captured since the context was created
 
   bool prof = false;
   struct Ev {
@@ -592,6 +593,7 @@ static rwpt_status enqueue_step(rwpt_ctx* c, bool sort, bool walk) {
 // sort that moves the masses flips once more.
 static int step_flips(const rwpt_ctx* c, bool sort) { return (sort && !masses_stay(c)) ? 0 : 1; }
 
+
 static rwpt_status ensure_sorted(rwpt_ctx* c) {
   if (c->sorted_valid) return RWPT_OK;
   rwpt_status st = enqueue_sort(c, false, true);  // masses follow into the sorted order
@@ -902,6 +904,7 @@ rwpt_status rwpt_step(rwpt_ctx* c, double dt, double D, int32_t n_steps) {
         hipError_t ei = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         HIPCHK(c, ei);
+        ++c->n_captures;
       }
       HIPCHK(c, hipGraphLaunch(gx, c->stream));
       c->mcur = m0 ^ step_flips(c, sort);
@@ -1093,6 +1096,65 @@ rwpt_status rwpt_neighbors(rwpt_ctx* c, double dt, double D, int64_t* rowptr, in
   return result;
 }
 
+rwpt_status rwpt_debug_rowsums(rwpt_ctx* c, double dt, double D, int32_t unit_weights, double* r_out) {
+  if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
+  c->err.clear();
+  if (!std::isfinite(dt) || dt <= 0.0 || !std::isfinite(D) || D < 0.0)
+    return fail(c, RWPT_EINVAL, "dt must be > 0 and D >= 0");
+  if (unit_weights != 0 && unit_weights != 1) return fail(c, RWPT_EINVAL, "unit_weights must be 0 or 1");
+  if (!c->initialized) return fail(c, RWPT_ESTATE, "debug_rowsums before rwpt_init_ensemble");
+  const int64_t N = c->N;
+  if (N > 0 && !r_out) return fail(c, RWPT_EINVAL, "r_out is NULL");
+  if (N == 0) return RWPT_OK;
+  if (c->dense) return fail(c, RWPT_EUNSUPPORTED, "the full-matrix path has no sparse row-sum pass");
+  HIPCHK(c, hipSetDevice(c->cfg.device));
+  rwpt_status st = build_grid(c, dt, D);
+  if (st != RWPT_OK) return st;
+  st = ensure_sorted(c);
+  if (st != RWPT_OK) return st;
+  PairArgs a = pair_args(c);
+  DevBuf rp_unit;
+  rwpt_status result = RWPT_OK;
+  do {
+    if (unit_weights) {
+      // every weight exp(0) = 1: r_i counts the neighbours within the cutoff
+      std::vector<RealParams> h = c->h_rp;
+      for (RealParams& P : h) {
+        P.escale_d = 0.0;
+        P.escale_f = 0.0f;
+      }
+      hipError_t e = rp_unit.ensure(h.size() * sizeof(RealParams));
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(rp_unit.p, h.data(), h.size() * sizeof(RealParams), hipMemcpyHostToDevice, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) {
+        result = fail(c, RWPT_EDEVICE, "debug_rowsums parameters: %s", hipGetErrorString(e));
+        break;
+      }
+      a.rp = rp_unit.as<RealParams>();
+    }
+    hipError_t e = launch_rowsum(c->cfg.precision == RWPT_FP64, c->dim, c->log2l, a, c->stream);
+    std::vector<double> hr(N);
+    std::vector<uint32_t> hid(N);
+    if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), c->r.p, N * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hid.data(), c->id.p, N * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      result = fail(c, RWPT_EDEVICE, "debug_rowsums: %s", hipGetErrorString(e));
+      break;
+    }
+    for (int64_t p = 0; p < N; ++p) {
+      if ((int64_t)hid[p] >= N) {
+        result = fail(c, RWPT_EDEVICE, "corrupt id map");
+        break;
+      }
+      r_out[hid[p]] = hr[p];
+    }
+  } while (0);
+  rp_unit.release();
+  return result;
+}
+
 rwpt_status rwpt_profile_enable(rwpt_ctx* c, int32_t on) {
   if (!c) return fail(nullptr, RWPT_EINVAL, "ctx is NULL");
   if (!on && c->prof) drain_profile(c);
@@ -1155,6 +1217,7 @@ rwpt_status rwpt_stats(rwpt_ctx* c, rwpt_stats_t* out) {
     if (st != RWPT_OK) return st;
   }
   out->n_phases = np;
+  out->graph_captures = c->n_captures;
   return RWPT_OK;
 }
 
@@ -1226,11 +1289,29 @@ static std::vector<std::pair<int, std::array<double, 3>>> tuning_candidates(int 
   return out;
 }
 
+// Everything that shapes the cell grids and the work of the pair kernels:
+// sizes, species, (dt, D), cutoff, precision, normalisation, walk share, the
+// box, the velocity and dispersivities, and the realisation sizes and D
+// scales (FNV-1a hash of their bits).
 static std::string tuning_key(const rwpt_ctx* c, double dt, double D) {
-  char buf[256];
-  snprintf(buf, sizeof(buf), "dim=%d N=%lld S=%d nreal=%d D=%.6g dt=%.6g kappa=%.6g prec=%d norm=%d rw=%.6g",
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t k = 0; k < n; ++k) {
+      h ^= b[k];
+      h *= 1099511628211ull;
+    }
+  };
+  mix(c->real_start.data(), c->real_start.size() * sizeof(int64_t));
+  mix(c->d_scale.data(), c->d_scale.size() * sizeof(double));
+  char buf[512];
+  snprintf(buf, sizeof(buf),
+           "dim=%d N=%lld S=%d nreal=%d D=%.6g dt=%.6g kappa=%.6g prec=%d norm=%d rw=%.6g "
+           "box=%.6g,%.6g,%.6g:%.6g,%.6g,%.6g v=%.6g,%.6g,%.6g aL=%.6g aT=%.6g real=%016llx",
            c->dim, (long long)c->N, c->S, c->n_real, D, dt, c->cfg.kappa, c->cfg.precision, c->cfg.norm,
-           c->cfg.rw_ratio);
+           c->cfg.rw_ratio, c->cfg.box_lo[0], c->cfg.box_lo[1], c->cfg.box_lo[2], c->cfg.box_hi[0],
+           c->cfg.box_hi[1], c->cfg.box_hi[2], c->cfg.velocity[0], c->cfg.velocity[1], c->cfg.velocity[2],
+           c->cfg.alpha_l, c->cfg.alpha_t, (unsigned long long)h);
   return buf;
 }
 
@@ -1339,7 +1420,17 @@ rwpt_status rwpt_autotune(rwpt_ctx* c, double dt, double D, int32_t trial_steps)
         result = fail(c, RWPT_EDEVICE, "autotune restore");
         break;
       }
-      rwpt_status st = rwpt_step(c, dt, D, 1);  // builds the grid, sorts, captures graphs
+      // untimed warm-up: builds the grid, sorts and captures the step graphs.
+      // A step's graph depends on the mass buffer it starts from, which
+      // alternates when the step flips it once (a sort that leaves the masses
+      // in place, or a step without a sort); three steps capture every graph
+      // the timed steps replay, so no capture falls inside the timed window.
+      const int warm = c->cfg.use_graph ? 3 : 1;
+      rwpt_status st = rwpt_step(c, dt, D, warm);
+      if (st == RWPT_EUNSUPPORTED) {
+        c->err.clear();  // e.g. a grid too large for this candidate: skip it
+        continue;
+      }
       if (st != RWPT_OK) {
         result = st;
         break;
@@ -1366,6 +1457,10 @@ rwpt_status rwpt_autotune(rwpt_ctx* c, double dt, double D, int32_t trial_steps)
     }
     c->prof = was_prof;
     if (result != RWPT_OK) break;
+    if (!(best_ms < INFINITY)) {
+      result = fail(c, RWPT_EUNSUPPORTED, "autotune: no candidate tiling is supported for this ensemble");
+      break;
+    }
     c->cfg.tile_lanes = best_lanes;
     for (int k = 0; k < 3; ++k) c->cfg.cell_refine[k] = best_ref[k];
     if (restore() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {

@@ -1139,13 +1139,81 @@ __device__ __forceinline__ int cell_of(const RealParams& P, int k, double v) {
   return (int)u;
 }
 
+// Candidate walk of the one-lane-per-particle kernels: the (y, z) rows of
+// cells that the lane's own cutoff box overlaps, each one contiguous sorted
+// range, taken kRowBatch rows at a time; their concatenation is walked
+// kCandBatch candidates per call of batch(jv, s2, ok) with all the batch's
+// position loads issued together.  jv: sorted indices; s2: squared
+// separations (sep2v, the cutoff predicate's arithmetic); ok: whether the
+// entry is a candidate (the tail of the last batch repeats particle ii).
+template <typename T, int DIM, typename BatchFn>
+__device__ __forceinline__ void priv_walk(const RealParams& P, const uint32_t* __restrict__ cell_start,
+                                          const T* __restrict__ pos, const T (&xi)[DIM], int32_t ii,
+                                          BatchFn&& batch) {
+  constexpr int RB = PrivBatch<DIM>::kRowBatch, CB = PrivBatch<DIM>::kCandBatch;
+  const double rg = P.rc_geo;
+  int ca[3] = {0, 0, 0}, cb_[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    ca[k] = cell_of(P, k, (double)xi[k] - rg);
+    cb_[k] = cell_of(P, k, (double)xi[k] + rg);
+  }
+  const int nyr = cb_[1] - ca[1] + 1;
+  const int nrows = nyr * (cb_[2] - ca[2] + 1);
+  const uint32_t nc0 = (uint32_t)P.nc[0], nc1 = (uint32_t)P.nc[1];
+  const uint32_t coff = (uint32_t)P.cell_off;
+  int yy = ca[1], zz = ca[2];
+  for (int r0 = 0; r0 < nrows; r0 += RB) {
+    uint32_t off[RB];
+    int32_t delta[RB];
+    uint32_t total = 0;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const bool in = r0 + q < nrows;
+      const uint32_t base = coff + ((uint32_t)zz * nc1 + (uint32_t)yy) * nc0;
+      const uint32_t jb = cell_start[base + (uint32_t)ca[0]];
+      const uint32_t je = cell_start[base + (uint32_t)cb_[0] + 1u];
+      off[q] = total;
+      delta[q] = (int32_t)jb - (int32_t)total;
+      total += in ? je - jb : 0u;
+      // next row: y fastest; past the last row (yy, zz) stays a valid cell
+      const bool wrap = yy == cb_[1];
+      const bool last = wrap && zz == cb_[2];
+      yy = last ? yy : (wrap ? ca[1] : yy + 1);
+      zz = last ? zz : (wrap ? zz + 1 : zz);
+    }
+    for (uint32_t t0 = 0; t0 < total; t0 += CB) {
+      uint32_t jv[CB];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        const uint32_t t = t0 + u;
+        int32_t d = delta[0];
+#pragma unroll
+        for (int q = 1; q < RB; ++q) d = t >= off[q] ? delta[q] : d;
+        jv[u] = t < total ? (uint32_t)((int32_t)t + d) : (uint32_t)ii;
+      }
+      T xj[CB][DIM];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) load_pos<T, DIM>(pos, jv[u], xj[u]);
+      T s2[CB];
+      bool ok[CB];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        s2[u] = sep2v<T, DIM>(xi, xj[u]);
+        ok[u] = t0 + u < total;
+      }
+      batch(jv, s2, ok);
+    }
+  }
+}
+
 template <typename T, int DIM, bool IND>
 __global__ __launch_bounds__(kBlock) void k_rowsum_priv(
     const T* __restrict__ pos, const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles,
     const int32_t ntiles, const RealParams* __restrict__ rp, double* __restrict__ r_out,
     T* __restrict__ q_out, uint16_t* __restrict__ nb_meta, uint32_t* __restrict__ nb_idx,
     T* __restrict__ nb_w, uint32_t* __restrict__ nb_src, const uint32_t* __restrict__ src_of) {
-  constexpr int RB = PrivBatch<DIM>::kRowBatch, CB = PrivBatch<DIM>::kCandBatch;
+  constexpr int CB = PrivBatch<DIM>::kCandBatch;
   WeightFn<T> wfn;  // before any return: the binary64 form has a block barrier
   wfn.setup();
   TileLane tl;
@@ -1166,68 +1234,24 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_priv(
   uint32_t cnt = 0;
   if (P.active && tl.valid) {
     acc = 0.0;
-    const double rg = P.rc_geo;
-    int ca[3] = {0, 0, 0}, cb_[3] = {0, 0, 0};
+    priv_walk<T, DIM>(P, cell_start, pos, xi, ii, [&](const uint32_t (&jv)[CB], const T (&s2)[CB],
+                                                      const bool (&ok)[CB]) {
+      T a = (T)0;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      ca[k] = cell_of(P, k, (double)xi[k] - rg);
-      cb_[k] = cell_of(P, k, (double)xi[k] + rg);
-    }
-    const int nyr = cb_[1] - ca[1] + 1;
-    const int nrows = nyr * (cb_[2] - ca[2] + 1);
-    const uint32_t nc0 = (uint32_t)P.nc[0], nc1 = (uint32_t)P.nc[1];
-    const uint32_t coff = (uint32_t)P.cell_off;
-    int yy = ca[1], zz = ca[2];
-    for (int r0 = 0; r0 < nrows; r0 += RB) {
-      uint32_t off[RB];
-      int32_t delta[RB];
-      uint32_t total = 0;
-#pragma unroll
-      for (int q = 0; q < RB; ++q) {
-        const bool in = r0 + q < nrows;
-        const uint32_t base = coff + ((uint32_t)zz * nc1 + (uint32_t)yy) * nc0;
-        const uint32_t jb = cell_start[base + (uint32_t)ca[0]];
-        const uint32_t je = cell_start[base + (uint32_t)cb_[0] + 1u];
-        off[q] = total;
-        delta[q] = (int32_t)jb - (int32_t)total;
-        total += in ? je - jb : 0u;
-        // next row: y fastest; past the last row (yy, zz) stays a valid cell
-        const bool wrap = yy == cb_[1];
-        const bool last = wrap && zz == cb_[2];
-        yy = last ? yy : (wrap ? ca[1] : yy + 1);
-        zz = last ? zz : (wrap ? zz + 1 : zz);
-      }
-      for (uint32_t t0 = 0; t0 < total; t0 += CB) {
-        uint32_t jv[CB];
-#pragma unroll
-        for (int u = 0; u < CB; ++u) {
-          const uint32_t t = t0 + u;
-          int32_t d = delta[0];
-#pragma unroll
-          for (int q = 1; q < RB; ++q) d = t >= off[q] ? delta[q] : d;
-          jv[u] = t < total ? (uint32_t)((int32_t)t + d) : (uint32_t)ii;
-        }
-        T xj[CB][DIM];
-#pragma unroll
-        for (int u = 0; u < CB; ++u) load_pos<T, DIM>(pos, jv[u], xj[u]);
-        T a = (T)0;
-#pragma unroll
-        for (int u = 0; u < CB; ++u) {
-          const T s2 = sep2v<T, DIM>(xi, xj[u]);
-          const T w = wfn(s2, esc);
-          const bool hit = t0 + u < total && s2 <= rc2;
-          a += hit ? w : (T)0;
-          if (hit && jv[u] != (uint32_t)ii && cnt <= (uint32_t)kCacheLane) {
-            if (cnt < (uint32_t)kCacheLane) {
-              lj[cnt * 64] = jv[u];
-              lw[cnt * 64] = w;
-            }
-            ++cnt;
+      for (int u = 0; u < CB; ++u) {
+        const T w = wfn(s2[u], esc);
+        const bool hit = ok[u] && s2[u] <= rc2;
+        a += hit ? w : (T)0;
+        if (hit && jv[u] != (uint32_t)ii && cnt <= (uint32_t)kCacheLane) {
+          if (cnt < (uint32_t)kCacheLane) {
+            lj[cnt * 64] = jv[u];
+            lw[cnt * 64] = w;
           }
+          ++cnt;
         }
-        acc += (double)a;
       }
-    }
+      acc += (double)a;
+    });
   }
   // wave-exclusive prefix of the kept counts (each at most kCacheLane < 16)
   const uint32_t keep = cnt <= (uint32_t)kCacheLane ? cnt : 0u;
@@ -1408,9 +1432,10 @@ __global__ __launch_bounds__(kBlock) void k_count(PairArgs a) {
 }
 
 // The same counts for the private-list kernels: every particle's candidates
-// are the cells of its own cutoff box, enumerated as k_rowsum_priv does.
+// are those of the row-sum pass's own walk (priv_walk).
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_count_priv(PairArgs a) {
+  constexpr int CB = PrivBatch<DIM>::kCandBatch;
   TileLane tl;
   Tile tile;
   if (!tile_lane_setup<0>(a.tiles, a.ntiles, tl, tile)) return;
@@ -1422,26 +1447,14 @@ __global__ __launch_bounds__(kBlock) void k_count_priv(PairArgs a) {
   const T rc2 = rc2_of<T>(P);
   unsigned long long pairs = 0, evals = 0;
   if (P.active && tl.valid) {
-    const double rg = P.rc_geo;
-    int ca[3] = {0, 0, 0}, cb_[3] = {0, 0, 0};
+    priv_walk<T, DIM>(P, a.cell_start, pos, xi, ii, [&](const uint32_t (&jv)[CB], const T (&s2)[CB],
+                                                        const bool (&ok)[CB]) {
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      ca[k] = cell_of(P, k, (double)xi[k] - rg);
-      cb_[k] = cell_of(P, k, (double)xi[k] + rg);
-    }
-    const uint32_t nc0 = (uint32_t)P.nc[0], nc1 = (uint32_t)P.nc[1];
-    const uint32_t coff = (uint32_t)P.cell_off;
-    for (int zz = ca[2]; zz <= cb_[2]; ++zz) {
-      for (int yy = ca[1]; yy <= cb_[1]; ++yy) {
-        const uint32_t base = coff + ((uint32_t)zz * nc1 + (uint32_t)yy) * nc0;
-        const uint32_t jb = a.cell_start[base + (uint32_t)ca[0]];
-        const uint32_t je = a.cell_start[base + (uint32_t)cb_[0] + 1u];
-        for (uint32_t j = jb; j < je; ++j) {
-          ++evals;
-          if (sep2<T, DIM>(xi, pos, j) <= rc2 && j != (uint32_t)ii) ++pairs;
-        }
+      for (int u = 0; u < CB; ++u) {
+        evals += ok[u] ? 1u : 0u;
+        pairs += (ok[u] && s2[u] <= rc2 && jv[u] != (uint32_t)ii) ? 1u : 0u;
       }
-    }
+    });
   }
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -1452,6 +1465,156 @@ __global__ __launch_bounds__(kBlock) void k_count_priv(PairArgs a) {
     const int t = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
     a.counts[2 * t] = pairs;
     a.counts[2 * t + 1] = evals;
+  }
+}
+
+// Neighbour pairs of the one-lane-per-particle tiling, through the row-sum
+// pass's own candidate walk and predicate: FILL = false counts per particle
+// (j = i included), FILL = true writes (i, j) sorted-slot pairs at
+// rowptr[i] + cursor.
+template <typename T, int DIM, bool FILL>
+__global__ __launch_bounds__(kBlock) void k_nbr_priv(PairArgs a) {
+  constexpr int CB = PrivBatch<DIM>::kCandBatch;
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<0>(a.tiles, a.ntiles, tl, tile)) return;
+  if (!tl.valid) return;
+  const RealParams& P = a.rp[tile.real];
+  const T* __restrict__ pos = (const T*)a.pos;
+  const int32_t ii = tl.i;
+  auto record = [&](uint32_t j) {
+    const uint32_t at = atomicAdd(&a.nbr_cursor[ii], 1u);
+    if (FILL) {
+      const unsigned long long o = a.nbr_rowptr[ii] + at;
+      a.nbr_pairs[2 * o] = (uint32_t)ii;
+      a.nbr_pairs[2 * o + 1] = j;
+    }
+  };
+  if (!P.active) {
+    record((uint32_t)ii);
+    return;
+  }
+  T xi[DIM];
+  load_pos<T, DIM>(pos, ii, xi);
+  const T rc2 = rc2_of<T>(P);
+  priv_walk<T, DIM>(P, a.cell_start, pos, xi, ii, [&](const uint32_t (&jv)[CB], const T (&s2)[CB],
+                                                      const bool (&ok)[CB]) {
+#pragma unroll
+    for (int u = 0; u < CB; ++u)
+      if (ok[u] && s2[u] <= rc2) record(jv[u]);
+  });
+}
+
+// Neighbour pairs and counts of the row-broadcast tiling (binary32, four lanes
+// per particle), through the chunk enumeration (for_tile_chunks, whole or
+// split tiles as the pair kernels are launched) and the per-candidate
+// predicate of row_weight.  MODE 0: per-particle counts (j = i included);
+// MODE 1: (i, j) pairs at rowptr[i] + cursor; MODE 2: per tile, the ordered
+// pairs j != i and the candidate evaluations the pair kernels perform (every
+// step of every chunk for every particle of the segment).
+template <int DIM, int SPLIT, int MODE>
+__global__ __launch_bounds__(kBlock) void k_nbr_dpp(PairArgs a) {
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<2, SPLIT>(a.tiles, a.ntiles, tl, tile)) return;  // block-uniform when SPLIT > 1
+  const int part = SPLIT > 1 ? (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0;
+  const RealParams& P = a.rp[tile.real];
+  const float* __restrict__ pos = (const float*)a.pos;
+  const int32_t ii = tl.valid ? tl.i : tile.end - 1;
+  float xi[DIM];
+  load_pos<float, DIM>(pos, ii, xi);
+  lane_cell<float, DIM>(P, a.skey, ii, tl);
+  const float rc2 = P.rc2_f;
+  unsigned long long pairs = 0, evals = 0;
+  auto record = [&](uint32_t j) {
+    const uint32_t at = atomicAdd(&a.nbr_cursor[tl.i], 1u);
+    if (MODE == 1) {
+      const unsigned long long o = a.nbr_rowptr[tl.i] + at;
+      a.nbr_pairs[2 * o] = (uint32_t)tl.i;
+      a.nbr_pairs[2 * o + 1] = j;
+    }
+  };
+  if (P.active) {
+    struct Cand {
+      float x[DIM];
+      int32_t j;
+      bool has;
+    };
+    for_tile_chunks<SPLIT>(
+        P, a.st, a.cell_start, tl, tile.begin, part,
+        [&](int32_t j, bool has) {
+          Cand d;
+          load_pos<float, DIM>(pos, j, d.x);
+          d.j = j;
+          d.has = has;
+          return d;
+        },
+        [&](const Cand& d, bool act) {
+          float xj[DIM];
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) xj[k] = d.x[k];
+          if (!d.has) xj[0] = 3.0e38f;
+          const float jf = __builtin_bit_cast(float, d.j);
+          const float hf = d.has ? 1.0f : 0.0f;
+          Steps<0, 16>::run([&](auto kc) {
+            constexpr int K = decltype(kc)::value;
+            // s^2 of the broadcast candidate exactly as row_weight forms it
+            const float d0 = rshare<K>(xj[0]) - xi[0];
+            float s2 = d0 * d0;
+            if constexpr (DIM > 1) {
+              const float d1 = rshare<K>(xj[1]) - xi[1];
+              s2 = __builtin_fmaf(d1, d1, s2);
+            }
+            if constexpr (DIM > 2) {
+              const float d2 = rshare<K>(xj[2]) - xi[2];
+              s2 = __builtin_fmaf(d2, d2, s2);
+            }
+            // every broadcast is read with all lanes enabled (a DPP read from
+            // a disabled lane does not deliver its value), then combined
+            const uint32_t jk = (uint32_t)__builtin_bit_cast(int32_t, rshare<K>(jf));
+            const float hk = rshare<K>(hf);
+            const bool hit = act & (hk != 0.0f) & (s2 <= rc2);
+            if constexpr (MODE == 2) {
+              evals += act ? 1u : 0u;
+              pairs += (hit && jk != (uint32_t)tl.i) ? 1u : 0u;
+            } else {
+              if (hit) record(jk);
+            }
+          });
+        });
+  } else if (MODE != 2 && tl.valid && tl.gl == 0 && part == 0) {
+    record((uint32_t)tl.i);  // only the self pair
+  }
+  if constexpr (MODE == 2) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      pairs += __shfl_xor(pairs, off);
+      evals += __shfl_xor(evals, off);
+    }
+    const int lane = threadIdx.x & 63;
+    if constexpr (SPLIT > 1) {
+      __shared__ unsigned long long shc[SPLIT][2];
+      if (lane == 0) {
+        shc[part][0] = pairs;
+        shc[part][1] = evals;
+      }
+      __syncthreads();
+      if (part == 0 && lane == 0) {
+        unsigned long long p = 0, e = 0;
+#pragma unroll
+        for (int w = 0; w < SPLIT; ++w) {
+          p += shc[w][0];
+          e += shc[w][1];
+        }
+        const int64_t t = wave_tile<SPLIT>();
+        a.counts[2 * t] = p;
+        a.counts[2 * t + 1] = e;
+      }
+    } else if (lane == 0) {
+      const int64_t t = wave_tile();
+      a.counts[2 * t] = pairs;
+      a.counts[2 * t + 1] = evals;
+    }
   }
 }
 
@@ -1841,6 +2004,24 @@ hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipS
   });
 }
 
+// The row-broadcast export/count kernels in the launch shape of the binary32
+// four-lane pair kernels (one block per tile up to kSplitTiles tiles).
+template <int MODE>
+static hipError_t launch_nbr_dpp(int dim, const PairArgs& a, hipStream_t s) {
+  const bool split = a.ntiles <= kSplitTiles;
+  const dim3 g = split ? dim3((unsigned)a.ntiles) : pair_grid(a.ntiles), b(kBlock);
+  auto go = [&](auto d) {
+    constexpr int D = decltype(d)::value;
+    if (split) hipLaunchKernelGGL((k_nbr_dpp<D, kBlock / 64, MODE>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_nbr_dpp<D, 1, MODE>), g, b, 0, s, a);
+  };
+  if (dim == 1) go(IC<1>{});
+  else if (dim == 2) go(IC<2>{});
+  else if (dim == 3) go(IC<3>{});
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
@@ -1849,30 +2030,39 @@ hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStre
       hipLaunchKernelGGL((k_count_priv<decltype(t), decltype(d)::value>), g, b, 0, s, a);
     });
   }
+  if (!fp64 && log2l == 2) return launch_nbr_dpp<2>(dim, a, s);
   return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
     using T = decltype(t);
     hipLaunchKernelGGL((k_count<T, decltype(d)::value, decltype(l)::value>), g, b, 0, s, a);
   });
 }
 
-hipError_t launch_nbr_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
+// The neighbour export enumerates the candidates exactly as the tiling the
+// step launches: the row-broadcast chunks (binary32, four lanes), the own
+// cutoff-box walk of the row-sum pass (one lane per particle), or the
+// stencil rows of the vector-load tiles.
+template <bool FILL>
+static hipError_t launch_nbr(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
-  if (log2l == kPrivateLists) log2l = 0;  // same tiles of 64
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
+  if (log2l == kPrivateLists) {
+    return dispatch_tdl(fp64, dim, 0, [&](auto t, auto d, auto) {
+      hipLaunchKernelGGL((k_nbr_priv<decltype(t), decltype(d)::value, FILL>), g, b, 0, s, a);
+    });
+  }
+  if (!fp64 && log2l == 2) return launch_nbr_dpp<FILL ? 1 : 0>(dim, a, s);
   return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
     using T = decltype(t);
-    hipLaunchKernelGGL((k_nbr<T, decltype(d)::value, decltype(l)::value, false>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_nbr<T, decltype(d)::value, decltype(l)::value, FILL>), g, b, 0, s, a);
   });
 }
 
+hipError_t launch_nbr_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
+  return launch_nbr<false>(fp64, dim, log2l, a, s);
+}
+
 hipError_t launch_nbr_fill(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
-  if (a.ntiles <= 0) return hipSuccess;
-  if (log2l == kPrivateLists) log2l = 0;  // same tiles of 64
-  const dim3 g = pair_grid(a.ntiles), b(kBlock);
-  return dispatch_tdl(fp64, dim, log2l, [&](auto t, auto d, auto l) {
-    using T = decltype(t);
-    hipLaunchKernelGGL((k_nbr<T, decltype(d)::value, decltype(l)::value, true>), g, b, 0, s, a);
-  });
+  return launch_nbr<true>(fp64, dim, log2l, a, s);
 }
 
 hipError_t launch_audit_reduce(const double* part, int32_t S1, const AuditChunk* chunks, int32_t nchunks,

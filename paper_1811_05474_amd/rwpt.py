@@ -30,7 +30,7 @@ EXPORTED = [
     "rwpt_config_default", "rwpt_create", "rwpt_init_ensemble", "rwpt_init_ensemble_device",
     "rwpt_step", "rwpt_sync", "rwpt_stats",
     "rwpt_query_masses", "rwpt_query_positions", "rwpt_audit", "rwpt_steps_taken",
-    "rwpt_count_pairs", "rwpt_neighbors", "rwpt_profile_enable", "rwpt_profile_reset",
+    "rwpt_count_pairs", "rwpt_neighbors", "rwpt_debug_rowsums", "rwpt_profile_enable", "rwpt_profile_reset",
     "rwpt_profile_read", "rwpt_profile_phase_name", "rwpt_probe_rate", "rwpt_get_tiling",
     "rwpt_autotune", "rwpt_last_error", "rwpt_version", "rwpt_destroy",
 ]
@@ -72,7 +72,7 @@ class rwpt_stats_t(ctypes.Structure):
         ("ordered_pairs", ctypes.c_int64),
         ("candidate_evals", ctypes.c_int64),
         ("n_phases", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
+        ("graph_captures", ctypes.c_int32),
         ("phase_ms", ctypes.c_double * 16),
         ("phase_launches", ctypes.c_int64 * 16),
     ]
@@ -113,6 +113,7 @@ def load_library(path: str | None = None):
         "rwpt_steps_taken": (i32, [vp, ctypes.POINTER(i64)]),
         "rwpt_count_pairs": (i32, [vp, f64, f64, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "rwpt_neighbors": (i32, [vp, f64, f64, vp, vp, ctypes.POINTER(i64)]),
+        "rwpt_debug_rowsums": (i32, [vp, f64, f64, i32, vp]),
         "rwpt_profile_enable": (i32, [vp, i32]),
         "rwpt_profile_reset": (i32, [vp]),
         "rwpt_profile_read": (i32, [vp, vp, vp, ctypes.POINTER(i32)]),
@@ -188,7 +189,7 @@ def rwpt_stats(ctx) -> dict:
     st = rwpt_stats_t()
     lib = load_library()
     _check(lib.rwpt_stats(ctx, ctypes.byref(st)), ctx)
-    out = {name: getattr(st, name) for name, _ in rwpt_stats_t._fields_ if name not in ("pad", "phase_ms", "phase_launches")}
+    out = {name: getattr(st, name) for name, _ in rwpt_stats_t._fields_ if name not in ("phase_ms", "phase_launches")}
     out["cell_refine"] = tuple(st.cell_refine)
     out["phases"] = {lib.rwpt_profile_phase_name(i).decode(): (float(st.phase_ms[i]), int(st.phase_launches[i]))
                      for i in range(st.n_phases)}
@@ -241,6 +242,12 @@ def rwpt_neighbors(ctx, dt: float, D: float, n: int):
     cols = np.zeros(max(1, nnz.value), dtype=np.int32)
     _check(lib.rwpt_neighbors(ctx, float(dt), float(D), _p(rowptr), _p(cols), ctypes.byref(nnz)), ctx)
     return rowptr, cols[: nnz.value]
+
+
+def rwpt_debug_rowsums(ctx, dt: float, D: float, n: int, unit_weights: bool = False) -> np.ndarray:
+    out = np.zeros(n, dtype=np.float64)
+    _check(load_library().rwpt_debug_rowsums(ctx, float(dt), float(D), 1 if unit_weights else 0, _p(out)), ctx)
+    return out
 
 
 def rwpt_profile_enable(ctx, on: bool):
@@ -362,6 +369,9 @@ class Ensemble:
 
     def neighbors(self, dt, D):
         return rwpt_neighbors(self.ctx, dt, D, self.n)
+
+    def rowsums(self, dt, D, unit_weights=False):
+        return rwpt_debug_rowsums(self.ctx, dt, D, self.n, unit_weights)
 
     def close(self):
         if self.ctx:

@@ -57,6 +57,25 @@ def normerr(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
+def check_pos(pos, ref, prec, xmax=1.0, ulps=2.0):
+    """Walked positions against the oracle's walk: within `ulps` units in the
+    last place of the largest coordinate (the premise of walk_tol)."""
+    u = float(np.spacing(np.float32(xmax))) if prec == F32 else float(np.spacing(np.float64(xmax)))
+    d = float(np.abs(pos - ref).max())
+    print("max position difference %.3e = %.2f ulp of %g" % (d, d / u, xmax))
+    assert d <= ulps * u, (d, d / u)
+
+
+def check_err(got, ref, bar, label=None):
+    """Normwise error max |got - ref| / max |ref| against its bar, printed so
+    that the margin under the bar is visible in the test log."""
+    err = normerr(got, ref)
+    print("normwise error %.3e (bar %.3e, margin %.1fx)%s"
+          % (err, bar, bar / max(err, 1e-300), "" if label is None else " [%s]" % (label,)))
+    assert err < bar, (err, bar, label)
+    return err
+
+
 def make(dim=2, S=2, react=(0, 1), kappa=3.0, rw=0.0, prec=F32, norm=rwpt.RWPT_NORM_SYM, lanes=0,
          refine=(0, 0, 0), graph=1, seed=1, box_lo=(0, 0, 0), box_hi=(1, 1, 1)):
     return rwpt.Ensemble(dim=dim, n_species=S, react=react, kappa=kappa, rw_ratio=rw, precision=prec,
@@ -86,7 +105,7 @@ def test_plain1d_n2000_full_run(prec, kappa, tol):
     pos = ens.positions()
     assert np.array_equal(pos, x)  # no walk: positions never move
     ref = oracle_run(x, M, w.D, w.dt, w.steps, kappa, 64 if prec == F64 else 32)
-    assert normerr(got, ref) < tol, normerr(got, ref)
+    check_err(got, ref, tol)
     a = ens.audit()[0]
     a0 = oracle.audit(M)
     cons_tol = 1e-12 if prec == F64 else 1e-6
@@ -104,7 +123,7 @@ def test_plain1d_n2000_row_normalisation(prec, tol, lanes):
     ens.init(sizes, x, M)
     ens.step(w.dt, w.D, 20)
     ref = oracle_run(x, M, w.D, w.dt, 20, 3.0, 64 if prec == F64 else 32, norm=oracle.NORM_ROW)
-    assert normerr(ens.masses(), ref) < tol
+    check_err(ens.masses(), ref, tol)
     ens.close()
 
 
@@ -119,7 +138,7 @@ def test_plain1d_n32768_sparse(lanes):
     ens.init(sizes, x, M)
     ens.step(w.dt, w.D, 3)
     ref = oracle_run(x, M, w.D, w.dt, 3, 3.0, 32)
-    assert normerr(ens.masses(), ref) < 1e-5
+    check_err(ens.masses(), ref, 1e-5)
     ens.close()
 
 
@@ -177,7 +196,7 @@ def test_lattice_pairs_exactly_at_the_cutoff(dim, lanes, prec):
     assert np.array_equal(np.diff(rp), expect)
     ens.step(dt, D, 1)
     ref = oracle_run(x, M, D, dt, 1, 3.0, 32 if prec == F32 else 64)
-    assert normerr(ens.masses(), ref) < (1e-5 if prec == F32 else 1e-12)
+    check_err(ens.masses(), ref, (1e-5 if prec == F32 else 1e-12))
     ens.close()
 
 
@@ -193,9 +212,9 @@ def test_walk2d_step_with_walk_replayed(prec, lanes):
     ens.init([n], x, M)
     for step, (xr, mr) in enumerate(OS.steps(x, M, 3, D, dt, seed, (0, 0), (1, 1), prec == F32)):
         ens.step(dt, D, 1)
-        assert np.abs(ens.positions() - xr).max() < (2e-6 if prec == F32 else 1e-12)
+        check_pos(ens.positions(), xr, prec)
         got = ens.masses()
-        assert normerr(got, mr) < walk_tol(prec, D, dt), (step, normerr(got, mr))
+        check_err(got, mr, walk_tol(prec, D, dt), step)
     ens.close()
 
 
@@ -212,8 +231,8 @@ def test_walk2d_n1e6_one_step_sampled(prec):
     got = ens.masses()
     rows = np.random.default_rng(5).choice(w.n, 4000, replace=False)
     (xr, ref), = OS.steps(x, M, 1, w.D, w.dt, w.seed, (0, 0), (1, 1), prec == F32, rows=rows)
-    assert np.abs(pos - xr).max() < (2e-6 if prec == F32 else 1e-12)
-    assert normerr(got[:, rows], ref) < walk_tol(prec, w.D, w.dt)
+    check_pos(pos, xr, prec)
+    check_err(got[:, rows], ref, walk_tol(prec, w.D, w.dt))
     # mean in-cutoff neighbours near the closed-form value for the unit square
     pairs, _ = ens.count_pairs(w.dt, w.D)
     r = 3 * math.sqrt(8 * w.D * w.dt)
@@ -241,8 +260,8 @@ def test_walk3d_n8e6_one_step_sampled(prec):
     got = ens.masses()
     rows = np.random.default_rng(6).choice(w.n, 4000, replace=False)
     (xr, ref), = OS.steps(x, M, 1, w.D, w.dt, w.seed, (0, 0, 0), (1, 1, 1), prec == F32, rows=rows)
-    assert np.abs(pos - xr).max() < (2e-6 if prec == F32 else 1e-12)
-    assert normerr(got[:, rows], ref) < walk_tol(prec, w.D, w.dt)
+    check_pos(pos, xr, prec)
+    check_err(got[:, rows], ref, walk_tol(prec, w.D, w.dt))
     # the binary64 audit of all eight species and of A - B over 8e6 particles
     # (many reduction chunks in one realisation) against exactly rounded sums
     ex = np.asarray(exact_sums(got))
@@ -290,7 +309,7 @@ def test_batched_realisations_match_independent_oracles():
     for r in range(len(sizes)):
         b, e = off[r], off[r + 1]
         ref = oracle_run(x[b:e], M[:, b:e], Ds[r], w.dt, 2, 3.0, 32)
-        assert normerr(got[:, b:e], ref) < 1e-5, r
+        check_err(got[:, b:e], ref, 1e-5, r)
         assert abs(a[r, 0] - exact_sums(got[:, b:e])[0]) < 1e-12
     ens.close()
 
@@ -316,9 +335,9 @@ def test_batch2d_64_full_size_sampled():
         # realisation r alone: its particles keep their global Philox ids
         walked = oracle.walk(x[b:e], np.arange(b, e, dtype=np.uint32), w.seed, 0, Ds[r], w.dt, (0, 0), (1, 1))
         xr = f32(walked)
-        assert np.abs(pos[b:e] - xr).max() < 2e-6, r
+        check_pos(pos[b:e], xr, F32)
         ref = oracle.transfer(xr, M[:, b:e], Ds[r], w.dt, kappa=3.0, prec=32, rows=rows)
-        assert normerr(got[:, b + rows], ref) < walk_tol(F32, Ds[r], w.dt), r
+        check_err(got[:, b + rows], ref, walk_tol(F32, Ds[r], w.dt), r)
     ens.close()
 
 
@@ -338,7 +357,7 @@ def test_batch_with_empty_and_single_realisations():
             continue
         b, e = off[r], off[r + 1]
         ref = oracle_run(x[b:e], M[:, b:e], D * [1, 1, 1, 1, 0.5, 1][r], dt, 2, 3.0, 64)
-        assert normerr(got[:, b:e], ref) < 1e-12
+        check_err(got[:, b:e], ref, 1e-12)
     ens.close()
 
 
@@ -364,7 +383,7 @@ def test_walk3d_eight_species(prec, lanes):
     ens.step(dt, D, 1)
     (xr, mr), = OS.steps(x, M, 1, D, dt, 55, (0, 0, 0), (1, 1, 1), prec == F32)
     assert np.abs(ens.positions() - xr).max() < (2e-6 if prec == F32 else 1e-12)
-    assert normerr(ens.masses(), mr) < walk_tol(prec, D, dt)
+    check_err(ens.masses(), mr, walk_tol(prec, D, dt))
     if ens.stats()["tile_lanes"] == -1:
         # one lane per particle: only the cells of its own cutoff box (about
         # 2 x 2 x 2 cells of two cutoffs, ~16 candidates here for ~2 neighbours
@@ -387,7 +406,7 @@ def test_walk3d_row_broadcast_tiles_whole_and_split():
         assert ens.stats()["tile_lanes"] == 4
         (xr, mr), = OS.steps(x, M, 1, D, dt, 56, (0, 0, 0), (1, 1, 1), True)
         assert np.abs(ens.positions() - xr).max() < 2e-6, n
-        assert normerr(ens.masses(), mr) < walk_tol(F32, D, dt), n
+        check_err(ens.masses(), mr, walk_tol(F32, D, dt), n)
         ens.close()
 
 
@@ -400,7 +419,7 @@ def test_species_counts_and_no_reaction(S):
     ens.init([n], x, M)
     ens.step(dt, D, 2)
     ref = oracle_run(x, M, D, dt, 2, 3.0, 64, react=None)
-    assert normerr(ens.masses(), ref) < 1e-12
+    check_err(ens.masses(), ref, 1e-12)
     a = ens.audit()[0]
     assert np.allclose(a[:S], M.sum(axis=1), rtol=1e-12, atol=0)
     ens.close()
@@ -416,7 +435,7 @@ def test_single_particle_and_ragged_sizes():
         ens.init([n], x, M)
         ens.step(0.1, 0.05, 1)
         ref = oracle_run(x, M, 0.05, 0.1, 1, 3.0, 64)
-        assert normerr(ens.masses(), ref) < 1e-12, n
+        check_err(ens.masses(), ref, 1e-12, n)
         ens.close()
 
 
@@ -428,7 +447,7 @@ def test_all_particles_coincident():
     ens.init([n], x, M)
     ens.step(0.1, 1e-4, 1)
     mean = M.mean(axis=1, keepdims=True)
-    assert normerr(ens.masses(), 0.5 * (M + mean)) < 1e-13
+    check_err(ens.masses(), 0.5 * (M + mean), 1e-13)
     ens.close()
 
 
@@ -446,7 +465,7 @@ def test_zero_diffusion_and_zero_steps():
     m = np.maximum(0, np.minimum(ref[0], ref[1]))
     ref[0] -= m
     ref[1] -= m
-    assert normerr(got, ref) < 1e-7
+    check_err(got, ref, 1e-7)
     assert np.array_equal(ens.positions(), x)
     ens.close()
 
@@ -461,7 +480,7 @@ def test_particles_on_the_walls_and_corners():
     ens.init([n], x, M)
     ens.step(0.1, 2e-3, 1)
     ref = oracle_run(x, M, 2e-3, 0.1, 1, 3.0, 64)
-    assert normerr(ens.masses(), ref) < 1e-12
+    check_err(ens.masses(), ref, 1e-12)
     ens.close()
 
 
@@ -474,7 +493,7 @@ def test_non_unit_box():
     ens.init([n], x, M)
     ens.step(0.1, 1e-3, 2)
     ref = oracle_run(x, M, 1e-3, 0.1, 2, 3.0, 32)
-    assert normerr(ens.masses(), ref) < 1e-5
+    check_err(ens.masses(), ref, 1e-5)
     ens.close()
 
 
@@ -488,7 +507,7 @@ def test_non_unit_box_3d():
         ens.init([n], x, M)
         ens.step(0.1, 1e-3, 2)
         ref = oracle_run(x, M, 1e-3, 0.1, 2, 3.0, 32)
-        assert normerr(ens.masses(), ref) < 1e-5, lanes
+        check_err(ens.masses(), ref, 1e-5, lanes)
         ens.close()
 
 
@@ -508,7 +527,7 @@ def test_other_cutoff_multiples(dim, kappa, lanes, prec):
     ens.init([n], x, M)
     ens.step(dt, D, 2)
     ref = oracle_run(x, M, D, dt, 2, kappa, 32 if prec == F32 else 64)
-    assert normerr(ens.masses(), ref) < (1e-5 if prec == F32 else 1e-12)
+    check_err(ens.masses(), ref, (1e-5 if prec == F32 else 1e-12))
     ens.close()
 
 
@@ -524,7 +543,7 @@ def test_cutoff_wider_than_the_box(dim):
     ens.step(dt, D, 1)
     assert ens.count_pairs(dt, D)[0] == n * (n - 1)
     ref = oracle_run(x, M, D, dt, 1, math.inf, 32)
-    assert normerr(ens.masses(), ref) < 1e-5
+    check_err(ens.masses(), ref, 1e-5)
     ens.close()
 
 
@@ -573,7 +592,7 @@ def test_autotune_restores_state_and_keeps_parity(tmp_path, monkeypatch):
     # the tuned context continues the oracle's own three-step trajectory
     xr, mr = list(OS.steps(f32(x), f32(M), 3, D, dt, 41, (0, 0), (1, 1), True))[-1]
     assert np.abs(ens.positions() - xr).max() < 2e-6
-    assert normerr(ens.masses(), mr) < walk_tol(F32, D, dt)
+    check_err(ens.masses(), mr, walk_tol(F32, D, dt))
     ens.close()
     # a second context with the same shape takes the cached choice
     text = (tmp_path / "tune.txt").read_text()
@@ -584,6 +603,25 @@ def test_autotune_restores_state_and_keeps_parity(tmp_path, monkeypatch):
     assert rwpt.rwpt_get_tiling(e2.ctx) == (lanes, ref)
     assert (tmp_path / "tune.txt").read_text() == text
     e2.close()
+
+
+@pytest.mark.parametrize("lanes", [-1, 1, 4, 8, 16])
+@pytest.mark.parametrize("rw", [1.0, 0.0])
+def test_three_warm_up_steps_capture_every_graph_the_timed_steps_replay(lanes, rw):
+    # the autotuner times each candidate tiling after three untimed steps; a
+    # step's graph depends on the mass buffer it starts from, so every graph
+    # that later steps replay must already exist after those three
+    n, D, dt = 20000, 2e-4, 0.1
+    ens = make(dim=2, rw=rw, prec=F32, seed=4, lanes=lanes)
+    ens.init([n], f32(W.positions(n, 2, 4)), f32(W.masses(n, 2, 4)))
+    ens.step(dt, D, 3)
+    before = ens.stats()["graph_captures"]
+    ens.step(dt, D, 5)
+    after = ens.stats()["graph_captures"]
+    print("lanes %d, walk %g: %d graphs captured in the warm-up, %d more in five steps" % (lanes, rw, before,
+                                                                                      after - before))
+    assert 1 <= before <= 4 and after == before
+    ens.close()
 
 
 # ------------------------------------------------- full matrix on MFMA ----
@@ -604,7 +642,7 @@ def test_dense_full_matrix_matches_oracle(dim, n, S, norm):
     ens.step(dt, D, steps)
     ref = oracle_run(x, M, D, dt, steps, math.inf, 32,
                      norm=oracle.NORM_SYM if norm == rwpt.RWPT_NORM_SYM else oracle.NORM_ROW, react=react)
-    assert normerr(ens.masses(), ref) < 1e-5, normerr(ens.masses(), ref)
+    check_err(ens.masses(), ref, 1e-5)
     if norm == rwpt.RWPT_NORM_SYM:
         # conserved by transfer and reaction: sum(A - B), or sum(M) without a reaction
         a0 = oracle.audit(M, react)
@@ -623,7 +661,7 @@ def test_dense_plain1d_n32768_two_steps_and_walk():
     ens.init(sizes, x, M)
     ens.step(w.dt, w.D, 2)
     ref = oracle_run(x, M, w.D, w.dt, 2, math.inf, 32)
-    assert normerr(ens.masses(), ref) < 1e-5
+    check_err(ens.masses(), ref, 1e-5)
     ens.close()
     # with the walk: one step against the oracle's own walk + full-matrix transfer
     n = 6000
@@ -635,7 +673,7 @@ def test_dense_plain1d_n32768_two_steps_and_walk():
     ens.step(0.1, 1e-3, 1)
     (xr, mr), = OS.steps(x, M, 1, 1e-3, 0.1, 9, (0, 0), (1, 1), True, kappa=math.inf)
     assert np.abs(ens.positions() - xr).max() < 2e-6
-    assert normerr(ens.masses(), mr) < walk_tol(F32, 1e-3, 0.1)
+    check_err(ens.masses(), mr, walk_tol(F32, 1e-3, 0.1))
     ens.close()
 
 
@@ -742,7 +780,7 @@ def test_private_lists_cached_and_missed_neighbours(dim, mean_nb, prec, norm):
         ens.step(dt, D, 1)
         pos, got = ens.positions(), ens.masses()
         assert np.abs(pos - xr).max() < (2e-6 if prec == F32 else 1e-12)
-        assert normerr(got, mr) < walk_tol(prec, D, dt), (step, normerr(got, mr))
+        check_err(got, mr, walk_tol(prec, D, dt), step)
     pairs, _ = ens.count_pairs(dt, D)
     assert 0.5 * mean_nb * n < pairs < 1.5 * mean_nb * n
     ens.close()
@@ -828,7 +866,7 @@ def test_dense_full_matrix_at_its_maximum_size():
     # the oracle at kappa = 7 equals its full matrix to e^-49 of the kernel
     # (far below any tolerance here) and runs on its cell grid
     ref = oracle.transfer(x, M, D, dt, kappa=7.0, prec=32, rows=rows)
-    assert normerr(got[:, rows], ref) < 1e-5
+    check_err(got[:, rows], ref, 1e-5)
     a = ens.audit()[0]
     assert abs(a[2] - oracle.audit(M)[2]) < 1e-6 * (a[0] + a[1])
     ens.close()
@@ -855,7 +893,7 @@ def test_advective_walk_replayed(dim, prec):
         ens.step(dt, D, 1)
         pos, got = ens.positions(), ens.masses()
         assert np.abs(pos - xr).max() < (2e-6 if prec == F32 else 1e-12)
-        assert normerr(got, mr) < walk_tol(prec, D, dt), (step, normerr(got, mr))
+        check_err(got, mr, walk_tol(prec, D, dt), step)
     ens.close()
 
 
@@ -953,7 +991,7 @@ def test_graph_eager_split_and_interleaved_queries_agree_bitwise(lanes, rw, prec
     if rw == 0.0:
         ref = oracle_run(f32(x) if prec == F32 else x, f32(M) if prec == F32 else M, D, dt, 7, 3.0,
                          32 if prec == F32 else 64)
-        assert normerr(runs[0][0], ref) < (1e-5 if prec == F32 else 1e-12)
+        check_err(runs[0][0], ref, (1e-5 if prec == F32 else 1e-12))
 
 
 def test_cell_grids_of_different_refinement_agree_over_steps():
@@ -974,7 +1012,7 @@ def test_cell_grids_of_different_refinement_agree_over_steps():
     (cells_a, m_a, x_a, p_a), (cells_b, m_b, x_b, p_b) = out
     assert 2 * cells_a < cells_b
     assert np.array_equal(x_a, x_b) and p_a == p_b
-    assert normerr(m_a, m_b) < 1e-12
+    check_err(m_a, m_b, 1e-12)
 
 
 def test_cell_scan_both_forms_agree():
@@ -995,4 +1033,102 @@ def test_cell_scan_both_forms_agree():
     (cells_big, m_big, p_big), (cells_small, m_small, p_small) = out
     assert cells_big > 256 * 4096 >= cells_small
     assert p_big == p_small
-    assert normerr(m_big, m_small) < 1e-12
+    check_err(m_big, m_small, 1e-12)
+
+
+# ----------------------- full sizes on identical positions (no walk) ----
+
+def default_lanes(dim, prec):
+    return {1: 4 if prec == F32 else 16, 2: 4 if prec == F32 else 8, 3: -1}[dim]
+
+
+@pytest.mark.parametrize("prec", [F32, F64])
+@pytest.mark.parametrize("name", ["walk2d_n1e6", "walk3d_n8e6_s8"])
+def test_full_size_transfer_on_identical_positions(name, prec):
+    """The 10^6-particle 2-D and 8e6-particle 3-D workloads in the launch
+    configuration the benchmark times, with the walk switched off so that both
+    sides see the same positions: two steps (the first sorts the seeded input,
+    and the one-lane-per-particle path then reads the masses through the
+    previous order; the second does not sort), sampled particles against the
+    oracle at the stated bars with no walk allowance."""
+    w = W.WORKLOADS[name]
+    x, M, sizes, _ = W.make_inputs(w)
+    if prec == F32:
+        x, M = f32(x), f32(M)
+    p = 32 if prec == F32 else 64
+    ens = make(dim=w.dim, S=w.n_species, rw=0.0, prec=prec, seed=w.seed)
+    ens.init(sizes, x, M)
+    rows = np.random.default_rng(21).choice(w.n, 4000, replace=False)
+    ens.step(w.dt, w.D, 1)
+    assert ens.stats()["tile_lanes"] == default_lanes(w.dim, prec)
+    m1 = oracle.transfer(x, M, w.D, w.dt, kappa=w.kappa, prec=p, react=w.react)
+    check_err(ens.masses()[:, rows], m1[:, rows], 1e-5 if prec == F32 else 1e-12, "step 1")
+    ens.step(w.dt, w.D, 1)
+    m2 = oracle.transfer(x, m1, w.D, w.dt, kappa=w.kappa, prec=p, react=w.react, rows=rows)
+    check_err(ens.masses()[:, rows], m2, 1e-5 if prec == F32 else 1e-12, "step 2")
+    ens.close()
+
+
+def test_batch2d_64_full_size_on_identical_positions():
+    """All 64 realisations (4.24e6 particles) in the benchmark's launch
+    configuration, walk off: sampled particles of the smallest, the largest
+    and two mid-size realisations after two steps at the binary32 bar."""
+    w = W.WORKLOADS["batch2d_64"]
+    x, M, sizes, Ds = W.make_inputs(w)
+    x, M = f32(x), f32(M)
+    ens = make(dim=2, rw=0.0, prec=F32, seed=w.seed)
+    ens.init(sizes, x, M, d_scale=Ds / w.D)
+    ens.step(w.dt, w.D, 2)
+    got = ens.masses()
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    order = np.argsort(sizes)
+    rng = np.random.default_rng(22)
+    for r in [int(order[0]), int(order[-1]), int(order[31]), int(order[32])]:
+        b, e = int(off[r]), int(off[r + 1])
+        rows = rng.choice(e - b, min(500, e - b), replace=False)
+        m1 = oracle.transfer(x[b:e], M[:, b:e], Ds[r], w.dt, kappa=3.0, prec=32)
+        ref = oracle.transfer(x[b:e], m1, Ds[r], w.dt, kappa=3.0, prec=32, rows=rows)
+        check_err(got[:, b + rows], ref, 1e-5, "realisation %d, %d particles, D %g" % (r, e - b, Ds[r]))
+    ens.close()
+
+
+# ---------------------------------------------- the stated run lengths ----
+
+def _long_runs():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_long_runs.py")
+    spec = importlib.util.spec_from_file_location("make_long_runs", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("run,prec,path", [("plain1d_n32768_k3_fp32", F32, rwpt.RWPT_PATH_SPARSE),
+                                           ("plain1d_n32768_k3_fp64", F64, rwpt.RWPT_PATH_SPARSE),
+                                           ("plain1d_n32768_k7_fp32", F32, rwpt.RWPT_PATH_DENSE),
+                                           ("walk2d_n1e6_rw0_fp32", F32, rwpt.RWPT_PATH_SPARSE),
+                                           ("walk2d_n1e6_rw0_fp64", F64, rwpt.RWPT_PATH_SPARSE)])
+def test_full_run_length_against_stored_oracle_runs(run, prec, path):
+    """The plain 1-D workload for its 500 steps (cutoff 3 sigma in both
+    precisions, and the full matrix on matrix cores against the oracle at
+    7 sigma, which equals the full matrix to e^-49 of the kernel) and the
+    10^6-particle 2-D workload for its 200 steps with positions fixed: the
+    error accumulated over the whole run against the oracle's run, written by
+    tests/golden/make_long_runs.py from the oracle alone."""
+    LR = _long_runs()
+    w, x, M, steps, kappa, p, rows_expected = LR.inputs(run)
+    rows, ref = LR.load(run)
+    assert np.array_equal(rows, rows_expected)
+    dense = path == rwpt.RWPT_PATH_DENSE
+    ens = rwpt.Ensemble(dim=w.dim, n_species=w.n_species, react=w.react, kappa=None if dense else kappa,
+                        rw_ratio=0.0, precision=prec, path=path, seed=w.seed)
+    ens.init([w.n], x, M)
+    ens.step(w.dt, w.D, steps)
+    got = ens.masses()
+    check_err(got[:, rows], ref, 1e-5 if prec == F32 else 1e-12, "%s after %d steps" % (run, steps))
+    a0, a1 = oracle.audit(M, w.react), ens.audit()[0]
+    drift = abs(a1[-1] - a0[-1]) / (a0[0] + a0[1])
+    print("sum(A - B) drift over the run %.2e of sum(A + B)" % drift)
+    assert drift < (1e-6 if prec == F32 else 1e-12)
+    ens.close()
