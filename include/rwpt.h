@@ -254,6 +254,37 @@ rwpt_status rwpt_get_tiling(rwpt_ctx *ctx, int32_t *tile_lanes, double *cell_ref
  * the file named by the environment variable RWPT_TUNE_CACHE if it is set. */
 rwpt_status rwpt_autotune(rwpt_ctx *ctx, double dt, double D, int32_t trial_steps);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * allocation-free form of one rwpt_step on a single realisation: one explicit
+ * transfer step (Sec. 1.1, Eqs. 3-6) with the reaction, without the walk, on
+ * n particles held in the caller's device arrays, computed by the same
+ * kernels as rwpt_step (cell sort, row sums, exchange) with cfg->path taken
+ * as SPARSE; cfg->rw_ratio, velocity and dispersivities are ignored.
+ *   pos:      device, n x dim row-major, binary32 (RWPT_FP32) or binary64
+ *             (RWPT_FP64) as cfg->precision says; positions inside the box
+ *             (not checked: the data stay on the device);
+ *   mass_in:  device, S x n species-major, same type;
+ *   mass_out: device, S x n species-major, same type; may not alias mass_in.
+ * Every intermediate lives in a fixed 64 MiB scratch area of the library on
+ * the current device (held until the process ends), so the call makes no
+ * device allocation and no host-device copy; it queues its kernels on
+ * cfg->stream (NULL = the device's default stream) and returns without
+ * waiting.  A call whose intermediates exceed the area (about 110 bytes per
+ * particle in 2-D binary32 with two species, about 340 in 3-D binary64 with
+ * eight species, cell counters included: some 6 * 10^5 and 2 * 10^5
+ * particles) or whose cutoff
+ * spans more than 64 stencil rows returns RWPT_EUNSUPPORTED before queuing
+ * anything.  Every call on one device shares that device's area and leaves
+ * its contents behind: calls that overlap on one device (other streams or
+ * host threads) race and must be serialised by the caller.  The first call on
+ * a device looks up the area's address; make it outside graph capture.
+ * Errors (message in rwpt_last_error(NULL)): RWPT_EINVAL (bad configuration,
+ * n, dt, D or pointers), RWPT_EUNSUPPORTED (dense path, size or stencil
+ * beyond the limits), RWPT_EDEVICE (no device, a launch failed). */
+rwpt_status rwpt_transfer_noalloc(const rwpt_config *cfg, int32_t n, const void *pos, const void *mass_in,
+                                  void *mass_out, double dt, double D);
+
 /* Message of the last failed call on this context ("" if none).  Valid until
  * the next call on the context. */
 const char *rwpt_last_error(const rwpt_ctx *ctx);

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -272,6 +273,108 @@ static void drain_profile(rwpt_ctx* c) {
 // grid, stencil and tiles for (dt, D)
 // ---------------------------------------------------------------------------
 
+// Cell grid, physical parameters and neighbour-row stencil of one realisation
+// of nr particles for the step (dt, D_r): the walk amplitudes (Eq. 1/2), the
+// cutoff kappa sigma with sigma^2 = 8 D_r dt and its binary32 / binary64
+// squares, the weight scale of Eq. 3, cells per axis (refine cells per cutoff
+// length, at most about four per particle), and the stencil rows appended to
+// st (P.stencil_off, P.n_stencil).  P.cell_off = cell_off; p_begin / p_end
+// are left to the caller.
+template <typename Rows>
+static void real_grid(const rwpt_config& cfg, int dim, double dt, double Dr, int64_t nr, const double refine[3],
+                      bool dense, float* dense_escale, float* dense_skip_s2, int64_t cell_off, RealParams& P,
+                      Rows& st) {
+  memset(&P, 0, sizeof(P));
+  double L[3];
+  for (int k = 0; k < 3; ++k) {
+    P.lo[k] = k < dim ? cfg.box_lo[k] : 0.0;
+    P.hi[k] = k < dim ? cfg.box_hi[k] : 1.0;
+    L[k] = P.hi[k] - P.lo[k];
+  }
+  {
+    // walk: isotropic share D_rw, plus drift and dispersion with a velocity
+    double speed2 = 0.0;
+    for (int k = 0; k < dim; ++k) speed2 += cfg.velocity[k] * cfg.velocity[k];
+    const double speed = std::sqrt(speed2);
+    const double Drw = cfg.rw_ratio * Dr;
+    P.amp = std::sqrt(2.0 * dt * (Drw + cfg.alpha_t * speed));
+    P.amp_x = std::sqrt(2.0 * dt * (Drw + cfg.alpha_l * speed)) - P.amp;
+    for (int k = 0; k < 3; ++k) {
+      P.drift[k] = k < dim ? cfg.velocity[k] * dt : 0.0;
+      P.udir[k] = (k < dim && speed > 0.0) ? cfg.velocity[k] / speed : 0.0;
+    }
+    P.moves = (P.amp > 0.0 || speed > 0.0) ? 1 : 0;
+  }
+  P.active = Dr > 0.0 ? 1 : 0;
+  int64_t nc[3] = {1, 1, 1};
+  double rcg = 0.0;
+  if (P.active) {
+    const double sigma2 = 8.0 * Dr * dt;
+    const double rc2 = std::isinf(cfg.kappa) ? INFINITY : cfg.kappa * cfg.kappa * sigma2;
+    P.rc2_d = rc2;
+    P.rc2_f = (float)rc2;
+    P.escale_d = -1.0 / sigma2;
+    P.escale_f = (float)(-1.4426950408889634073599246810019 / sigma2);
+    // geometric cutoff: covers the rounding of s^2 in the predicate
+    rcg = std::sqrt(rc2) * (1.0 + 1e-5);
+    P.rc_geo = rcg;
+    if (dense) {
+      // every pair counts; the grid only orders particles so that 32-particle
+      // column tiles are compact, and tiles farther apart than the distance
+      // where w < 2^-40 are skipped
+      *dense_escale = P.escale_f;
+      *dense_skip_s2 = (float)(41.0 / std::fabs((double)P.escale_f));
+      rcg = std::sqrt(40.0 / std::fabs((double)P.escale_f));
+    }
+    if (std::isfinite(rcg)) {
+      for (int k = 0; k < dim; ++k) {
+        double v = std::floor(L[k] * refine[k] / rcg);
+        if (!(v >= 1.0)) v = 1.0;
+        if (v > (double)(1 << 20)) v = (double)(1 << 20);
+        nc[k] = (int64_t)v;
+      }
+      const int64_t cap_cells = std::max<int64_t>(4 * nr, 64);
+      for (;;) {
+        int64_t prod = nc[0] * nc[1] * nc[2];
+        if (prod <= cap_cells) break;
+        int kmax = 0;
+        for (int k = 1; k < 3; ++k)
+          if (nc[k] > nc[kmax]) kmax = k;
+        if (nc[kmax] <= 1) break;
+        nc[kmax] = (nc[kmax] + 1) / 2;
+      }
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    P.nc[k] = (int32_t)nc[k];
+    P.inv_h[k] = (double)nc[k] / L[k];
+  }
+  P.cell_off = cell_off;
+  P.stencil_off = (int32_t)st.size();
+  if (P.active && !dense) {
+    const double h[3] = {L[0] / nc[0], L[1] / nc[1], L[2] / nc[2]};
+    int Ry = 0, Rz = 0;
+    if (dim >= 2) Ry = std::isfinite(rcg) ? (int)std::min<double>(nc[1] - 1, std::ceil(rcg / h[1])) : (int)nc[1] - 1;
+    if (dim >= 3) Rz = std::isfinite(rcg) ? (int)std::min<double>(nc[2] - 1, std::ceil(rcg / h[2])) : (int)nc[2] - 1;
+    for (int dz = -Rz; dz <= Rz; ++dz)
+      for (int dy = -Ry; dy <= Ry; ++dy) {
+        int rx;
+        if (std::isfinite(rcg)) {
+          const double ym = std::max(0, std::abs(dy) - 1) * h[1];
+          const double zm = std::max(0, std::abs(dz) - 1) * h[2];
+          const double rem = rcg * rcg - ym * ym - zm * zm;
+          if (rem < 0.0) continue;
+          const double hw = std::sqrt(rem);
+          rx = (int)std::min<double>(nc[0] - 1, std::ceil(hw * P.inv_h[0]));
+        } else {
+          rx = (int)nc[0] - 1;
+        }
+        st.push_back(StencilRow{dy, dz, rx, 0});
+      }
+  }
+  P.n_stencil = (int32_t)st.size() - P.stencil_off;
+}
+
 static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   if (c->grid_valid && c->g_dt == dt && c->g_D == D) return RWPT_OK;
   const rwpt_config& cfg = c->cfg;
@@ -291,100 +394,12 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   int64_t cell_off = 0;
   for (int r = 0; r < c->n_real; ++r) {
     RealParams& P = c->h_rp[r];
-    memset(&P, 0, sizeof(P));
-    double L[3];
-    for (int k = 0; k < 3; ++k) {
-      P.lo[k] = k < dim ? cfg.box_lo[k] : 0.0;
-      P.hi[k] = k < dim ? cfg.box_hi[k] : 1.0;
-      L[k] = P.hi[k] - P.lo[k];
-    }
+    const int64_t nr = c->real_start[r + 1] - c->real_start[r];
+    real_grid(cfg, dim, dt, D * c->d_scale[r], nr, c->refine, c->dense, &c->dense_escale, &c->dense_skip_s2,
+              cell_off, P, c->h_st);
     P.p_begin = c->real_start[r];
     P.p_end = c->real_start[r + 1];
-    const int64_t nr = P.p_end - P.p_begin;
-    const double Dr = D * c->d_scale[r];
-    {
-      // walk: isotropic share D_rw, plus drift and dispersion with a velocity
-      double speed2 = 0.0;
-      for (int k = 0; k < dim; ++k) speed2 += cfg.velocity[k] * cfg.velocity[k];
-      const double speed = std::sqrt(speed2);
-      const double Drw = cfg.rw_ratio * Dr;
-      P.amp = std::sqrt(2.0 * dt * (Drw + cfg.alpha_t * speed));
-      P.amp_x = std::sqrt(2.0 * dt * (Drw + cfg.alpha_l * speed)) - P.amp;
-      for (int k = 0; k < 3; ++k) {
-        P.drift[k] = k < dim ? cfg.velocity[k] * dt : 0.0;
-        P.udir[k] = (k < dim && speed > 0.0) ? cfg.velocity[k] / speed : 0.0;
-      }
-      P.moves = (P.amp > 0.0 || speed > 0.0) ? 1 : 0;
-    }
-    P.active = Dr > 0.0 ? 1 : 0;
-    int64_t nc[3] = {1, 1, 1};
-    double rcg = 0.0;
-    if (P.active) {
-      const double sigma2 = 8.0 * Dr * dt;
-      const double rc2 = std::isinf(cfg.kappa) ? INFINITY : cfg.kappa * cfg.kappa * sigma2;
-      P.rc2_d = rc2;
-      P.rc2_f = (float)rc2;
-      P.escale_d = -1.0 / sigma2;
-      P.escale_f = (float)(-1.4426950408889634073599246810019 / sigma2);
-      // geometric cutoff: covers the rounding of s^2 in the predicate
-      rcg = std::sqrt(rc2) * (1.0 + 1e-5);
-      P.rc_geo = rcg;
-      if (c->dense) {
-        // every pair counts; the grid only orders particles so that 32-particle
-        // column tiles are compact, and tiles farther apart than the distance
-        // where w < 2^-40 are skipped
-        c->dense_escale = P.escale_f;
-        c->dense_skip_s2 = (float)(41.0 / std::fabs((double)P.escale_f));
-        rcg = std::sqrt(40.0 / std::fabs((double)P.escale_f));
-      }
-      if (std::isfinite(rcg)) {
-        for (int k = 0; k < dim; ++k) {
-          double v = std::floor(L[k] * c->refine[k] / rcg);
-          if (!(v >= 1.0)) v = 1.0;
-          if (v > (double)(1 << 20)) v = (double)(1 << 20);
-          nc[k] = (int64_t)v;
-        }
-        const int64_t cap_cells = std::max<int64_t>(4 * nr, 64);
-        for (;;) {
-          int64_t prod = nc[0] * nc[1] * nc[2];
-          if (prod <= cap_cells) break;
-          int kmax = 0;
-          for (int k = 1; k < 3; ++k)
-            if (nc[k] > nc[kmax]) kmax = k;
-          if (nc[kmax] <= 1) break;
-          nc[kmax] = (nc[kmax] + 1) / 2;
-        }
-      }
-    }
-    for (int k = 0; k < 3; ++k) {
-      P.nc[k] = (int32_t)nc[k];
-      P.inv_h[k] = (double)nc[k] / L[k];
-    }
-    P.cell_off = cell_off;
-    cell_off += nc[0] * nc[1] * nc[2];
-    P.stencil_off = (int32_t)c->h_st.size();
-    if (P.active && !c->dense) {
-      const double h[3] = {L[0] / nc[0], L[1] / nc[1], L[2] / nc[2]};
-      int Ry = 0, Rz = 0;
-      if (dim >= 2) Ry = std::isfinite(rcg) ? (int)std::min<double>(nc[1] - 1, std::ceil(rcg / h[1])) : (int)nc[1] - 1;
-      if (dim >= 3) Rz = std::isfinite(rcg) ? (int)std::min<double>(nc[2] - 1, std::ceil(rcg / h[2])) : (int)nc[2] - 1;
-      for (int dz = -Rz; dz <= Rz; ++dz)
-        for (int dy = -Ry; dy <= Ry; ++dy) {
-          int rx;
-          if (std::isfinite(rcg)) {
-            const double ym = std::max(0, std::abs(dy) - 1) * h[1];
-            const double zm = std::max(0, std::abs(dz) - 1) * h[2];
-            const double rem = rcg * rcg - ym * ym - zm * zm;
-            if (rem < 0.0) continue;
-            const double hw = std::sqrt(rem);
-            rx = (int)std::min<double>(nc[0] - 1, std::ceil(hw * P.inv_h[0]));
-          } else {
-            rx = (int)nc[0] - 1;
-          }
-          c->h_st.push_back(StencilRow{dy, dz, rx, 0});
-        }
-    }
-    P.n_stencil = (int32_t)c->h_st.size() - P.stencil_off;
+    cell_off += (int64_t)P.nc[0] * P.nc[1] * P.nc[2];
     c->h_tile_start[r] = (int32_t)c->h_tiles.size();
     for (int64_t b = P.p_begin; b < P.p_end; b += G)
       c->h_tiles.push_back(Tile{(int32_t)b, (int32_t)std::min<int64_t>(b + G, P.p_end), r, 0});
@@ -606,41 +621,71 @@ static rwpt_status ensure_sorted(rwpt_ctx* c) {
 // C ABI
 // ---------------------------------------------------------------------------
 
-extern "C" {
+// ---------------------------------------------------------------------------
+// Scratch area of the allocation-free entry point
+// ---------------------------------------------------------------------------
 
-const char* rwpt_version(void) { return "rwpt-mi355x 0.1 (gfx950)"; }
+// Device memory of rwpt_transfer_noalloc: one fixed area per device, part of
+// the library's code object (held by every device the library is loaded on
+// until the process ends).  Host code never uses the name `scratch` as an
+// address: it looks up the area's device address once per device.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
-void rwpt_config_default(rwpt_config* cfg) {
-  if (!cfg) return;
-  memset(cfg, 0, sizeof(*cfg));
-  cfg->dim = 2;
-  cfg->n_species = 2;
-  cfg->react_a = 0;
-  cfg->react_b = 1;
-  for (int k = 0; k < 3; ++k) {
-    cfg->box_lo[k] = 0.0;
-    cfg->box_hi[k] = 1.0;
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};  // device address of `scratch` on each device
+}  // namespace
+
+// Device address of the scratch area on the current device, looked up on the
+// first call on that device (with it current).
+static rwpt_status scratch_on_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kScratchDevices) {
+    (void)hipGetLastError();
+    return fail(nullptr, RWPT_EDEVICE, "no current HIP device (%s)", e != hipSuccess ? hipGetErrorString(e) : "ordinal out of range");
   }
-  cfg->kappa = 3.0;
-  cfg->rw_ratio = 1.0;
-  cfg->precision = RWPT_FP32;
-  cfg->norm = RWPT_NORM_SYM;
-  cfg->path = RWPT_PATH_AUTO;
-  cfg->tile_lanes = 0;
-  cfg->device = 0;
-  cfg->use_graph = 1;
-  cfg->seed = 0;
-  cfg->stream = nullptr;
-  for (int k = 0; k < 3; ++k) cfg->velocity[k] = 0.0;
-  cfg->alpha_l = 0.0;
-  cfg->alpha_t = 0.0;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(nullptr, RWPT_EDEVICE, "scratch area of device %d: %s", dev,
+                  e != hipSuccess ? hipGetErrorString(e) : "null address");
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RWPT_OK;
 }
 
-rwpt_status rwpt_create(const rwpt_config* cfg, rwpt_ctx** out) {
-  if (!out) return fail(nullptr, RWPT_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!cfg) return fail(nullptr, RWPT_EINVAL, "cfg is NULL");
-  const rwpt_config& c = *cfg;
+// Fixed-capacity list of stencil rows (no host allocation).
+struct RowBuf {
+  StencilRow* rows;
+  int cap;
+  int n;
+  size_t size() const { return (size_t)n; }
+  void push_back(const StencilRow& r) {
+    if (n < cap) rows[n] = r;
+    ++n;
+  }
+};
+
+// Bump allocation of 256-byte-aligned pieces of the scratch area.
+struct ScratchLayout {
+  size_t used = 0;
+  size_t take(size_t bytes) {
+    const size_t at = used;
+    used += (bytes + 255) / 256 * 256;
+    return at;
+  }
+};
+
+// Validation of a configuration (the messages go to the thread's error slot).
+static rwpt_status check_config(const rwpt_config& c) {
   if (c.dim < 1 || c.dim > 3) return fail(nullptr, RWPT_EINVAL, "dim must be 1, 2 or 3 (got %d)", c.dim);
   if (c.n_species < 1 || c.n_species > 8)
     return fail(nullptr, RWPT_EINVAL, "n_species must be in 1..8 (got %d)", c.n_species);
@@ -677,6 +722,46 @@ rwpt_status rwpt_create(const rwpt_config* cfg, rwpt_ctx** out) {
       return fail(nullptr, RWPT_EINVAL, "cell_refine[%d] must be in [0, 64]", k);
   if (c.device < 0) return fail(nullptr, RWPT_EINVAL, "device must be >= 0");
   if (c.use_graph != 0 && c.use_graph != 1) return fail(nullptr, RWPT_EINVAL, "use_graph must be 0 or 1");
+  return RWPT_OK;
+}
+
+extern "C" {
+
+const char* rwpt_version(void) { return "rwpt-mi355x 0.1 (gfx950)"; }
+
+void rwpt_config_default(rwpt_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->dim = 2;
+  cfg->n_species = 2;
+  cfg->react_a = 0;
+  cfg->react_b = 1;
+  for (int k = 0; k < 3; ++k) {
+    cfg->box_lo[k] = 0.0;
+    cfg->box_hi[k] = 1.0;
+  }
+  cfg->kappa = 3.0;
+  cfg->rw_ratio = 1.0;
+  cfg->precision = RWPT_FP32;
+  cfg->norm = RWPT_NORM_SYM;
+  cfg->path = RWPT_PATH_AUTO;
+  cfg->tile_lanes = 0;
+  cfg->device = 0;
+  cfg->use_graph = 1;
+  cfg->seed = 0;
+  cfg->stream = nullptr;
+  for (int k = 0; k < 3; ++k) cfg->velocity[k] = 0.0;
+  cfg->alpha_l = 0.0;
+  cfg->alpha_t = 0.0;
+}
+
+rwpt_status rwpt_create(const rwpt_config* cfg, rwpt_ctx** out) {
+  if (!out) return fail(nullptr, RWPT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(nullptr, RWPT_EINVAL, "cfg is NULL");
+  const rwpt_config& c = *cfg;
+  rwpt_status st = check_config(c);
+  if (st != RWPT_OK) return st;
   rwpt_ctx* ctx = new (std::nothrow) rwpt_ctx();
   if (!ctx) return fail(nullptr, RWPT_ENOMEM, "out of host memory");
   ctx->cfg = c;
@@ -1494,6 +1579,134 @@ rwpt_status rwpt_autotune(rwpt_ctx* c, double dt, double D, int32_t trial_steps)
   sa.release();
   sc.release();
   return result;
+}
+
+rwpt_status rwpt_transfer_noalloc(const rwpt_config* cfg, int32_t n, const void* pos, const void* mass_in,
+                                  void* mass_out, double dt, double D) {
+  if (!cfg) return fail(nullptr, RWPT_EINVAL, "cfg is NULL");
+  const rwpt_config& c = *cfg;
+  rwpt_status st = check_config(c);
+  if (st != RWPT_OK) return st;
+  if (c.path == RWPT_PATH_DENSE)
+    return fail(nullptr, RWPT_EUNSUPPORTED, "rwpt_transfer_noalloc runs the sparse path only");
+  if (n < 0 || n > INT32_MAX - 64) return fail(nullptr, RWPT_EINVAL, "n must be in 0..2^31 - 65 (got %d)", n);
+  if (!std::isfinite(dt) || dt <= 0.0) return fail(nullptr, RWPT_EINVAL, "dt must be finite and > 0");
+  if (!std::isfinite(D) || D < 0.0) return fail(nullptr, RWPT_EINVAL, "D must be finite and >= 0");
+  if (n > 0 && (!pos || !mass_in || !mass_out)) return fail(nullptr, RWPT_EINVAL, "pos/mass_in/mass_out is NULL");
+  if (n > 0 && (mass_in == mass_out)) return fail(nullptr, RWPT_EINVAL, "mass_out may not alias mass_in");
+  if (n == 0) return RWPT_OK;
+  const int dim = c.dim, S = c.n_species;
+  const int fp64 = c.precision == RWPT_FP64;
+  const size_t ts = fp64 ? 8 : 4;
+  const int lanes = c.tile_lanes ? c.tile_lanes : default_lanes(dim, n, fp64);
+  const int log2l = lanes_to_log2(lanes);
+  const int G = log2l == kPrivateLists ? 64 : 64 >> log2l;
+  double refine[3], defr[3];
+  default_refine(dim, defr);
+  for (int k = 0; k < 3; ++k) refine[k] = c.cell_refine[k] > 0 ? c.cell_refine[k] : defr[k];
+  // grid of the realisation for (dt, D): parameters and stencil rows, kept in
+  // kernel arguments
+  NoAllocParams na;
+  memset(&na, 0, sizeof(na));
+  RowBuf rows{na.st, kNoAllocStencil, 0};
+  float unused_escale = 0.0f, unused_skip = 0.0f;
+  real_grid(c, dim, dt, D, n, refine, false, &unused_escale, &unused_skip, 0, na.P, rows);
+  if (rows.n > kNoAllocStencil)
+    return fail(nullptr, RWPT_EUNSUPPORTED, "the cutoff spans %d stencil rows; the allocation-free path takes at most %d",
+                rows.n, kNoAllocStencil);
+  na.n_st = rows.n;
+  na.P.p_begin = 0;
+  na.P.p_end = n;
+  const int64_t ncell = (int64_t)na.P.nc[0] * na.P.nc[1] * na.P.nc[2];
+  const int32_t ntiles = (int32_t)((n + G - 1) / G);
+  const int64_t cap = (int64_t)(n + 63) / 64 * 64;
+  const int PS = dim == 3 ? 4 : dim, Sa = padded_species(S);
+  const int64_t nscan = (ncell + kScanChunk - 1) / kScanChunk + 1;
+  // the pieces of the scratch area this call uses
+  ScratchLayout L;
+  const size_t o_pos0 = L.take(PS * cap * ts), o_pos1 = L.take(PS * cap * ts);
+  const size_t o_m0 = L.take(Sa * cap * ts), o_m1 = L.take(Sa * cap * ts);
+  const size_t o_id = L.take(cap * 4), o_key = L.take(cap * 4), o_slot = L.take(cap * 4);
+  const size_t o_tsrc = L.take(cap * 4), o_tid = L.take(cap * 4), o_tkey = L.take(cap * 4);
+  const size_t o_skey = L.take(cap * 4), o_r = L.take(cap * 8), o_q = L.take(cap * ts);
+  const size_t o_cnt = L.take(ncell * 4), o_start = L.take((ncell + 1) * 4), o_scan = L.take(nscan * 4);
+  const size_t o_rp = L.take(sizeof(RealParams)), o_st = L.take(kNoAllocStencil * sizeof(StencilRow));
+  const size_t o_tiles = L.take((size_t)ntiles * sizeof(Tile));
+  const size_t o_blk = L.take((size_t)((n + kBlock - 1) / kBlock) * 4), o_ctr = L.take(8);
+  const size_t o_rs = L.take(2 * sizeof(int64_t));
+  const size_t o_aud = L.take((size_t)ntiles * (S + 1) * 8);
+  size_t o_meta = 0, o_nidx = 0, o_nw = 0, o_nsrc = 0;
+  if (log2l == kPrivateLists) {
+    o_meta = L.take(cap * 2);
+    o_nidx = L.take((size_t)ntiles * kCacheWave * 4);
+    o_nw = L.take((size_t)ntiles * kCacheWave * ts);
+    o_nsrc = L.take((size_t)ntiles * kCacheWave * 4);
+  }
+  if (L.used > kScratchBytes)
+    return fail(nullptr, RWPT_EUNSUPPORTED,
+                "%d particles (dim %d, %d species, binary%d, %lld cells) need %zu bytes of scratch; "
+                "the allocation-free path has %zu",
+                n, dim, S, fp64 ? 64 : 32, (long long)ncell, L.used, kScratchBytes);
+  void* base = nullptr;
+  st = scratch_on_current_device(&base);
+  if (st != RWPT_OK) return st;
+  unsigned char* b = (unsigned char*)base;
+  auto at = [&](size_t off) { return (void*)(b + off); };
+  hipStream_t s = (hipStream_t)c.stream;
+#define NACHK(expr)                                                                                 \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
+    if (e_ != hipSuccess) {                                                                         \
+      (void)hipGetLastError();                                                                      \
+      return fail(nullptr, RWPT_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));                   \
+    }                                                                                               \
+  } while (0)
+  // set-up: parameters, stencil, tiles, ids, cleared counts, caller layouts
+  NACHK(launch_noalloc_setup(fp64, dim, S, na, n, pos, mass_in, at(o_pos0), at(o_m0), (uint32_t*)at(o_id),
+                             (Tile*)at(o_tiles), G, ntiles, (RealParams*)at(o_rp), (StencilRow*)at(o_st),
+                             (int64_t*)at(o_rs), (int32_t*)at(o_blk), (uint32_t*)at(o_cnt), ncell, s));
+  // cell keys (no walk), counting sort, canonical order with the masses moved
+  NACHK(launch_walk_key(fp64, dim, at(o_pos0), at(o_pos1), (uint32_t*)at(o_id), n, (RealParams*)at(o_rp),
+                        (int64_t*)at(o_rs), (int32_t*)at(o_blk), 1, (uint64_t*)at(o_ctr), c.seed, 0, (uint32_t*)at(o_cnt),
+                        (uint32_t*)at(o_key), (uint32_t*)at(o_slot), s));
+  NACHK(launch_cell_scan((uint32_t*)at(o_cnt), (uint32_t*)at(o_start), ncell, (uint32_t*)at(o_scan), s));
+  NACHK(launch_scatter(n, (uint32_t*)at(o_key), (uint32_t*)at(o_slot), (uint32_t*)at(o_start), (uint32_t*)at(o_id),
+                       (uint32_t*)at(o_tsrc), (uint32_t*)at(o_tid), (uint32_t*)at(o_tkey), s));
+  NACHK(launch_canon(fp64, dim, n, (uint32_t*)at(o_tsrc), (uint32_t*)at(o_tid), (uint32_t*)at(o_tkey),
+                     (uint32_t*)at(o_start), at(o_pos1), at(o_pos0), at(o_m0), at(o_m1), S, (uint32_t*)at(o_id),
+                     (uint32_t*)at(o_skey), nullptr, s));
+  // row sums, then the exchange + reaction into the other mass buffer
+  PairArgs a;
+  memset(&a, 0, sizeof(a));
+  a.pos = at(o_pos0);
+  a.mass_in = at(o_m1);
+  a.mass_out = at(o_m0);
+  a.q_in = at(o_q);
+  a.q_out = at(o_q);
+  a.r_out = (double*)at(o_r);
+  a.skey = (uint32_t*)at(o_skey);
+  a.cell_start = (uint32_t*)at(o_start);
+  a.tiles = (Tile*)at(o_tiles);
+  a.ntiles = ntiles;
+  a.rp = (RealParams*)at(o_rp);
+  a.st = (StencilRow*)at(o_st);
+  a.S = S;
+  a.react_a = c.react_a;
+  a.react_b = c.react_b;
+  a.norm = c.norm;
+  a.audit_part = (double*)at(o_aud);
+  if (log2l == kPrivateLists) {
+    a.nb_meta = (uint16_t*)at(o_meta);
+    a.nb_idx = (uint32_t*)at(o_nidx);
+    a.nb_w = at(o_nw);
+    a.nb_src = (uint32_t*)at(o_nsrc);
+  }
+  a.indirect = 0;
+  if (c.norm == RWPT_NORM_SYM || log2l == kPrivateLists) NACHK(launch_rowsum(fp64, dim, log2l, a, s));
+  NACHK(launch_exchange(fp64, dim, log2l, a, s));
+  NACHK(launch_noalloc_store(fp64, S, n, at(o_m0), (uint32_t*)at(o_id), mass_out, s));
+#undef NACHK
+  return RWPT_OK;
 }
 
 const char* rwpt_last_error(const rwpt_ctx* c) {

@@ -96,6 +96,27 @@ hipError_t launch_audit_reduce(const double* part, int32_t S1, const AuditChunk*
                                double* out, uint32_t* done, uint64_t* step_ctr, int32_t bump,
                                hipStream_t s);
 
+// Allocation-free transfer of one realisation in caller arrays.  Its grid
+// parameters and stencil rows travel as kernel arguments (at most
+// kNoAllocStencil rows) and are written to device memory by the set-up
+// launch, which also converts the caller's layouts (positions n x dim
+// row-major, masses S x n species-major), fills the tiles of G particles, the
+// realisation starts {0, n} and the walk's realisation table, and clears ncell
+// cell counts.
+constexpr int kNoAllocStencil = 64;
+struct NoAllocParams {
+  RealParams P;
+  StencilRow st[kNoAllocStencil];
+  int32_t n_st;
+};
+hipError_t launch_noalloc_setup(int fp64, int dim, int S, const NoAllocParams& a, int32_t n, const void* pos,
+                                const void* mass, void* pos_out, void* mass_out, uint32_t* id, Tile* tiles,
+                                int32_t G, int32_t ntiles, RealParams* rp, StencilRow* st, int64_t* real_start,
+                                int32_t* blk_real, uint32_t* cell_count, int64_t ncell, hipStream_t s);
+// Sorted masses (particle-major) back to the caller's order (S x n species-major).
+hipError_t launch_noalloc_store(int fp64, int S, int32_t n, const void* mass_sorted, const uint32_t* id,
+                                void* mass, hipStream_t s);
+
 // Full-matrix path of one realisation (binary32 state, bf16-split MFMA).
 struct DenseArgs {
   const float* pos;        // [cap][PS] particle-major, sorted

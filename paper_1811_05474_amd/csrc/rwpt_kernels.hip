@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 #include "rwpt_kernels.h"
@@ -1775,6 +1777,72 @@ __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ par
 }
 
 // ---------------------------------------------------------------------------
+// Allocation-free transfer of one realisation held in caller arrays: set-up
+// kernels that write the step's parameters, stencil, tiles and cleared cell
+// counts from kernel arguments, convert the caller's layouts, and return the
+// new masses in the caller's order.
+// ---------------------------------------------------------------------------
+
+// Parameters and stencil rows (one block): kernel arguments -> device memory.
+__global__ __launch_bounds__(kBlock) void k_na_params(NoAllocParams a, RealParams* __restrict__ rp,
+                                                      StencilRow* __restrict__ st, int64_t* __restrict__ real_start) {
+  if (threadIdx.x == 0) {
+    rp[0] = a.P;
+    real_start[0] = a.P.p_begin;
+    real_start[1] = a.P.p_end;
+  }
+  if ((int)threadIdx.x < a.n_st) st[threadIdx.x] = a.st[threadIdx.x];
+}
+
+// Grid-stride: ids 0..n-1, positions (n x DIM row-major) and masses (S x n
+// species-major) into the particle-major layouts (unused species slots zero),
+// tiles of G consecutive particles, the walk's per-block realisation table
+// (all zero: one realisation) and cleared cell counts.
+template <typename T, int DIM, int SP>
+__global__ __launch_bounds__(kBlock) void k_na_load(int32_t n, int32_t S, const T* __restrict__ pos,
+                                                    const T* __restrict__ mass, T* __restrict__ pos_out,
+                                                    T* __restrict__ mass_out, uint32_t* __restrict__ id,
+                                                    Tile* __restrict__ tiles, int32_t G, int32_t ntiles,
+                                                    int32_t* __restrict__ blk_real, int32_t nblk,
+                                                    uint32_t* __restrict__ cell_count, int64_t ncell) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  const int64_t top = ncell > n ? ncell : n;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < top; i += stride) {
+    if (i < n) {
+      id[i] = (uint32_t)i;
+      T x[DIM];
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) x[k] = pos[i * DIM + k];
+      store_pos<T, DIM>(pos_out, i, x);
+      T m[SP];
+#pragma unroll
+      for (int sp = 0; sp < SP; ++sp) m[sp] = sp < S ? mass[(int64_t)sp * n + i] : (T)0;
+      store_mass<T, SP>(mass_out, i, m);
+    }
+    if (i < ntiles) {
+      const int32_t b = (int32_t)i * G;
+      tiles[i] = Tile{b, b + G < n ? b + G : n, 0, 0};
+    }
+    if (i < nblk) blk_real[i] = 0;
+    if (i < ncell) cell_count[i] = 0u;
+  }
+}
+
+// Sorted particle p's new masses to the caller's order (S x n species-major).
+template <typename T, int SP>
+__global__ __launch_bounds__(kBlock) void k_na_store(int32_t n, int32_t S, const T* __restrict__ mass_sorted,
+                                                     const uint32_t* __restrict__ id, T* __restrict__ mass) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n) return;
+  T m[SP];
+  load_mass<T, SP>(mass_sorted, p, m);
+  const uint32_t o = id[p];
+#pragma unroll
+  for (int sp = 0; sp < SP; ++sp)
+    if (sp < S) mass[(int64_t)sp * n + o] = m[sp];
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 
@@ -2063,6 +2131,54 @@ hipError_t launch_nbr_count(int fp64, int dim, int log2l, const PairArgs& a, hip
 
 hipError_t launch_nbr_fill(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   return launch_nbr<true>(fp64, dim, log2l, a, s);
+}
+
+hipError_t launch_noalloc_setup(int fp64, int dim, int S, const NoAllocParams& a, int32_t n, const void* pos,
+                                const void* mass, void* pos_out, void* mass_out, uint32_t* id, Tile* tiles,
+                                int32_t G, int32_t ntiles, RealParams* rp, StencilRow* st, int64_t* real_start,
+                                int32_t* blk_real, uint32_t* cell_count, int64_t ncell, hipStream_t s) {
+  if (a.n_st < 0 || a.n_st > kNoAllocStencil) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_na_params, dim3(1), dim3(kBlock), 0, s, a, rp, st, real_start);
+  const int32_t nblk = (int32_t)blocks_for(n);
+  const int64_t top = std::max<int64_t>(ncell, n);
+  const unsigned g = (unsigned)std::min<int64_t>((top + kBlock - 1) / kBlock, 2048);
+  auto go = [&](auto t, auto d, auto sp) {
+    using T = decltype(t);
+    hipLaunchKernelGGL((k_na_load<T, decltype(d)::value, decltype(sp)::value>), dim3(g), dim3(kBlock), 0, s, n, S,
+                       (const T*)pos, (const T*)mass, (T*)pos_out, (T*)mass_out, id, tiles, G, ntiles, blk_real,
+                       nblk, cell_count, ncell);
+  };
+  auto with_s = [&](auto t, auto d) {
+    if (S <= 2) go(t, d, IC<2>{});
+    else if (S <= 4) go(t, d, IC<4>{});
+    else go(t, d, IC<8>{});
+  };
+  auto with_d = [&](auto t) {
+    if (dim == 1) with_s(t, IC<1>{});
+    else if (dim == 2) with_s(t, IC<2>{});
+    else with_s(t, IC<3>{});
+  };
+  if (fp64) with_d(double{});
+  else with_d(float{});
+  return hipGetLastError();
+}
+
+hipError_t launch_noalloc_store(int fp64, int S, int32_t n, const void* mass_sorted, const uint32_t* id,
+                                void* mass, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  auto go = [&](auto t, auto sp) {
+    using T = decltype(t);
+    hipLaunchKernelGGL((k_na_store<T, decltype(sp)::value>), dim3(blocks_for(n)), dim3(kBlock), 0, s, n, S,
+                       (const T*)mass_sorted, id, (T*)mass);
+  };
+  auto with_s = [&](auto t) {
+    if (S <= 2) go(t, IC<2>{});
+    else if (S <= 4) go(t, IC<4>{});
+    else go(t, IC<8>{});
+  };
+  if (fp64) with_s(double{});
+  else with_s(float{});
+  return hipGetLastError();
 }
 
 hipError_t launch_audit_reduce(const double* part, int32_t S1, const AuditChunk* chunks, int32_t nchunks,

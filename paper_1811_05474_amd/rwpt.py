@@ -32,7 +32,7 @@ EXPORTED = [
     "rwpt_query_masses", "rwpt_query_positions", "rwpt_audit", "rwpt_steps_taken",
     "rwpt_count_pairs", "rwpt_neighbors", "rwpt_debug_rowsums", "rwpt_profile_enable", "rwpt_profile_reset",
     "rwpt_profile_read", "rwpt_profile_phase_name", "rwpt_probe_rate", "rwpt_get_tiling",
-    "rwpt_autotune", "rwpt_last_error", "rwpt_version", "rwpt_destroy",
+    "rwpt_autotune", "rwpt_transfer_noalloc", "rwpt_last_error", "rwpt_version", "rwpt_destroy",
 ]
 
 
@@ -121,6 +121,7 @@ def load_library(path: str | None = None):
         "rwpt_probe_rate": (i32, [vp, i32, ctypes.POINTER(f64)]),
         "rwpt_get_tiling": (i32, [vp, ctypes.POINTER(i32), vp]),
         "rwpt_autotune": (i32, [vp, f64, f64, i32]),
+        "rwpt_transfer_noalloc": (i32, [pcfg, i32, vp, vp, vp, f64, f64]),
         "rwpt_last_error": (ctypes.c_char_p, [vp]),
         "rwpt_version": (ctypes.c_char_p, []),
         "rwpt_destroy": (None, [vp]),
@@ -283,6 +284,17 @@ def rwpt_get_tiling(ctx):
 
 def rwpt_autotune(ctx, dt: float, D: float, trial_steps: int = 3):
     _check(load_library().rwpt_autotune(ctx, float(dt), float(D), int(trial_steps)), ctx)
+
+
+def rwpt_transfer_noalloc(cfg: rwpt_config, n: int, pos_dev_ptr: int, mass_in_dev_ptr: int,
+                          mass_out_dev_ptr: int, dt: float, D: float):
+    """pos / mass_in / mass_out: device addresses (e.g. ``tensor.data_ptr()``)
+    of contiguous arrays in the path's precision: positions n x dim, masses
+    S x n.  Queued on cfg.stream; returns without waiting."""
+    st = load_library().rwpt_transfer_noalloc(ctypes.byref(cfg), int(n), ctypes.c_void_p(pos_dev_ptr),
+                                              ctypes.c_void_p(mass_in_dev_ptr), ctypes.c_void_p(mass_out_dev_ptr),
+                                              float(dt), float(D))
+    _check(st, None)
 
 
 def rwpt_last_error(ctx=None) -> str:
