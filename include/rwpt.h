@@ -89,7 +89,10 @@ typedef struct rwpt_config {
   int32_t tile_lanes;     /* lanes sharing one particle in the pair kernels, which then
                              share one candidate list per tile: 1, 4, 8 or 16;
                              -1 = one lane per particle with its own candidate rows
-                             (sparse neighbourhoods); 0 = choose from dim and N */
+                             (sparse neighbourhoods); -2 = half stencil (binary32):
+                             every unordered pair evaluated once and its share
+                             delivered to both ends (Sec. 6.1: about half as many
+                             operations), deterministic; 0 = choose from dim and N */
   double cell_refine[3];  /* cells per cutoff length along each axis (> 0); 0 = choose */
   int32_t device;         /* HIP device ordinal */
   int32_t use_graph;      /* 1 = replay each rwpt_step as one captured HIP graph */

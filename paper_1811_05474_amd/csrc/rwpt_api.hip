@@ -83,6 +83,8 @@ struct rwpt_ctx {
   DevBuf d_rp, d_st, d_tiles, d_tile_start, d_real_start, d_blk_real;
   DevBuf audit_part, audit_out, step_ctr, counts, d_chunks, d_chunk_start, chunk_part, audit_done;
   DevBuf bbox, bparts;  // full-matrix path
+  DevBuf half_slots, half_own, d_item_start;  // half-stencil tiling
+  int64_t half_nitems = 0;
   bool dense = false;   // full-matrix path selected at init
   float dense_escale = 0.0f, dense_skip_s2 = 0.0f;
   int64_t ncell_total = 0;
@@ -146,6 +148,7 @@ static rwpt_status fail(rwpt_ctx* c, rwpt_status st, const char* fmt, ...) {
 static int lanes_to_log2(int lanes) {
   switch (lanes) {
     case -1: return kPrivateLists;
+    case -2: return kHalfPairs;
     case 1: return 0;
     case 4: return 2;
     case 8: return 3;
@@ -375,6 +378,23 @@ static void real_grid(const rwpt_config& cfg, int dim, double dt, double Dr, int
   P.n_stencil = (int32_t)st.size() - P.stencil_off;
 }
 
+// Segments of the half-stencil tiling for one realisation: seg_w = twice the
+// widest reach along x of its stencil rows (so at most two segments of a row,
+// of different parity, reach any cell), the own row's reach, and the number
+// of forward stencil rows (dz > 0, or dz = 0 and dy > 0).
+static void half_segments(RealParams& P, const StencilRow* st) {
+  int rx_max = 0, rx_own = 0, n_fwd = 0;
+  for (int f = 0; f < P.n_stencil; ++f) {
+    rx_max = std::max(rx_max, st[f].rx);
+    if (st[f].dy == 0 && st[f].dz == 0) rx_own = st[f].rx;
+    if (st[f].dz > 0 || (st[f].dz == 0 && st[f].dy > 0)) ++n_fwd;
+  }
+  P.seg_w = std::max(1, 2 * rx_max);
+  P.nseg = P.active ? (P.nc[0] + P.seg_w - 1) / P.seg_w : 0;
+  P.rx_own = rx_own;
+  P.n_fwd = n_fwd;
+}
+
 static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   if (c->grid_valid && c->g_dt == dt && c->g_D == D) return RWPT_OK;
   const rwpt_config& cfg = c->cfg;
@@ -385,7 +405,8 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   double defr[3];
   default_refine(dim, defr);
   for (int k = 0; k < 3; ++k) c->refine[k] = cfg.cell_refine[k] > 0 ? cfg.cell_refine[k] : defr[k];
-  const int G = c->log2l == kPrivateLists ? 64 : 64 >> c->log2l;
+  const int G = (c->log2l == kPrivateLists || c->log2l == kHalfPairs) ? 64 : 64 >> c->log2l;
+  const bool half = c->log2l == kHalfPairs;
 
   c->h_rp.assign(c->n_real, RealParams{});
   c->h_st.clear();
@@ -400,6 +421,7 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
     P.p_begin = c->real_start[r];
     P.p_end = c->real_start[r + 1];
     cell_off += (int64_t)P.nc[0] * P.nc[1] * P.nc[2];
+    if (half) half_segments(P, c->h_st.data() + P.stencil_off);
     c->h_tile_start[r] = (int32_t)c->h_tiles.size();
     for (int64_t b = P.p_begin; b < P.p_end; b += G)
       c->h_tiles.push_back(Tile{(int32_t)b, (int32_t)std::min<int64_t>(b + G, P.p_end), r, 0});
@@ -417,6 +439,21 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   c->h_chunk_start[c->n_real] = (int32_t)c->h_chunks.size();
   if (cell_off >= (int64_t)1 << 31) return fail(c, RWPT_EUNSUPPORTED, "cell grid too large (%lld cells)", (long long)cell_off);
   c->ntiles = (int32_t)c->h_tiles.size();
+  // half-stencil tiling: work items (row, segment) of every realisation, and
+  // slot planes 2 (1 + forward rows) deep
+  std::vector<int64_t> item_start(c->n_real + 1, 0);
+  int max_fwd = 0;
+  c->half_nitems = 0;
+  if (half) {
+    for (int r = 0; r < c->n_real; ++r) {
+      RealParams& P = c->h_rp[r];
+      P.item_off = c->half_nitems;
+      item_start[r] = c->half_nitems;
+      c->half_nitems += (int64_t)P.nseg * P.nc[1] * P.nc[2];
+      max_fwd = std::max(max_fwd, P.n_fwd);
+    }
+    item_start[c->n_real] = c->half_nitems;
+  }
 
   // device copies
   const int64_t ncell = cell_off;
@@ -436,6 +473,14 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
     HIPCHK(c, c->nb_idx.ensure((size_t)std::max(1, c->ntiles) * kCacheWave * sizeof(uint32_t)));
     HIPCHK(c, c->nb_w.ensure((size_t)std::max(1, c->ntiles) * kCacheWave * c->tsize));
     HIPCHK(c, c->nb_src.ensure((size_t)std::max(1, c->ntiles) * kCacheWave * sizeof(uint32_t)));
+  }
+  if (half) {
+    const int Sa = padded_species(c->S);
+    HIPCHK(c, c->half_slots.ensure((size_t)2 * (1 + max_fwd) * c->cap * Sa * sizeof(float)));
+    HIPCHK(c, c->half_own.ensure((size_t)c->cap * Sa * sizeof(double)));
+    HIPCHK(c, c->d_item_start.ensure(item_start.size() * sizeof(int64_t)));
+    HIPCHK(c, hipMemcpyAsync(c->d_item_start.p, item_start.data(), item_start.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, c->stream));
   }
   if (c->dense) {
     const int ncb = dense_ncb(c->S, c->cfg.norm);
@@ -506,6 +551,12 @@ static PairArgs pair_args(rwpt_ctx* c) {
   a.nb_src = c->nb_src.as<uint32_t>();
   a.src_of = c->src_of.as<uint32_t>();
   a.indirect = 0;
+  a.half_slots = c->half_slots.as<float>();
+  a.half_own = c->half_own.as<double>();
+  a.half_item_start = c->d_item_start.as<int64_t>();
+  a.half_nitems = c->half_nitems;
+  a.half_cap = c->cap;
+  a.n_real = c->n_real;
   return a;
 }
 
@@ -586,7 +637,7 @@ static rwpt_status enqueue_step(rwpt_ctx* c, bool sort, bool walk) {
   } else {
     // the one-lane-per-particle exchange reads the row-sum pass's neighbour
     // cache, so that pass runs for either normalisation
-    if (c->cfg.norm == RWPT_NORM_SYM || c->log2l == kPrivateLists) {
+    if (c->cfg.norm == RWPT_NORM_SYM || c->log2l == kPrivateLists || c->log2l == kHalfPairs) {
       PhaseScope ps(c, PH_ROWSUM);
       HIPCHK(c, launch_rowsum(fp64, c->dim, c->log2l, a, c->stream));
     }
@@ -716,7 +767,9 @@ static rwpt_status check_config(const rwpt_config& c) {
   if (c.path == RWPT_PATH_DENSE && c.precision != RWPT_FP32)
     return fail(nullptr, RWPT_EUNSUPPORTED, "the dense (matrix-core) path is binary32 only");
   if (c.tile_lanes != 0 && lanes_to_log2(c.tile_lanes) == -2)
-    return fail(nullptr, RWPT_EINVAL, "tile_lanes must be -1, 0, 1, 4, 8 or 16 (got %d)", c.tile_lanes);
+    return fail(nullptr, RWPT_EINVAL, "tile_lanes must be -2, -1, 0, 1, 4, 8 or 16 (got %d)", c.tile_lanes);
+  if (c.tile_lanes == -2 && c.precision != RWPT_FP32)
+    return fail(nullptr, RWPT_EUNSUPPORTED, "the half-stencil tiling (tile_lanes -2) is binary32 only");
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(c.cell_refine[k]) || c.cell_refine[k] < 0.0 || c.cell_refine[k] > 64.0)
       return fail(nullptr, RWPT_EINVAL, "cell_refine[%d] must be in [0, 64]", k);
@@ -1287,7 +1340,7 @@ rwpt_status rwpt_stats(rwpt_ctx* c, rwpt_stats_t* out) {
     if (st != RWPT_OK) return st;
   }
   if (c->initialized && c->grid_valid) {
-    out->tile_lanes = c->log2l == kPrivateLists ? -1 : (1 << c->log2l);
+    out->tile_lanes = c->log2l == kPrivateLists ? -1 : (c->log2l == kHalfPairs ? -2 : (1 << c->log2l));
     for (int k = 0; k < 3; ++k) out->cell_refine[k] = c->refine[k];
     out->n_cells = c->ncell_total;
     int64_t pairs = 0, evals = 0;
@@ -1363,14 +1416,15 @@ rwpt_status rwpt_get_tiling(rwpt_ctx* c, int32_t* tile_lanes, double* cell_refin
 }
 
 // Candidate tilings per dimension: lanes per particle x cells per cutoff.
-static std::vector<std::pair<int, std::array<double, 3>>> tuning_candidates(int dim) {
+static std::vector<std::pair<int, std::array<double, 3>>> tuning_candidates(int dim, bool fp64) {
   std::vector<std::array<double, 3>> refs;
   if (dim == 1) refs = {{4, 1, 1}, {8, 1, 1}, {16, 1, 1}, {32, 1, 1}};
   else if (dim == 2) refs = {{8, 1, 1}, {16, 1, 1}, {4, 2, 1}, {8, 2, 1}, {8, 3, 1}, {16, 3, 1}, {8, 4, 1}};
   else refs = {{0.5, 0.5, 0.5}, {1, 0.5, 0.5}, {2, 1, 1}, {4, 1, 1}, {8, 1, 1}, {4, 2, 2}, {8, 0.5, 0.5}};
   std::vector<std::pair<int, std::array<double, 3>>> out;
-  for (int lanes : {-1, 1, 4, 8, 16})
-    for (auto& r : refs) out.push_back({lanes, r});
+  for (int lanes : {-2, -1, 1, 4, 8, 16})
+    if (lanes != -2 || !fp64)
+      for (auto& r : refs) out.push_back({lanes, r});
   return out;
 }
 
@@ -1498,7 +1552,7 @@ rwpt_status rwpt_autotune(rwpt_ctx* c, double dt, double D, int32_t trial_steps)
     float best_ms = INFINITY;
     const bool was_prof = c->prof;
     c->prof = false;
-    for (auto& cand : tuning_candidates(c->dim)) {
+    for (auto& cand : tuning_candidates(c->dim, c->cfg.precision == RWPT_FP64)) {
       c->cfg.tile_lanes = cand.first;
       for (int k = 0; k < 3; ++k) c->cfg.cell_refine[k] = cand.second[k];
       if (restore() != hipSuccess) {
@@ -1599,6 +1653,8 @@ rwpt_status rwpt_transfer_noalloc(const rwpt_config* cfg, int32_t n, const void*
   const int fp64 = c.precision == RWPT_FP64;
   const size_t ts = fp64 ? 8 : 4;
   const int lanes = c.tile_lanes ? c.tile_lanes : default_lanes(dim, n, fp64);
+  if (lanes == -2)
+    return fail(nullptr, RWPT_EUNSUPPORTED, "rwpt_transfer_noalloc does not take the half-stencil tiling");
   const int log2l = lanes_to_log2(lanes);
   const int G = log2l == kPrivateLists ? 64 : 64 >> log2l;
   double refine[3], defr[3];
@@ -1728,7 +1784,7 @@ void rwpt_destroy(rwpt_ctx* c) {
                       &c->d_tile_start, &c->d_real_start, &c->d_blk_real, &c->audit_part, &c->audit_out,
                       &c->step_ctr, &c->counts, &c->d_chunks, &c->d_chunk_start, &c->chunk_part,
                       &c->audit_done, &c->bbox, &c->bparts, &c->nb_meta, &c->nb_idx, &c->nb_w,
-                      &c->nb_src, &c->src_of};
+                      &c->nb_src, &c->src_of, &c->half_slots, &c->half_own, &c->d_item_start};
     for (DevBuf* b : bufs) b->release();
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }

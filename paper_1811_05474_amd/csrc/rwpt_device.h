@@ -28,7 +28,13 @@ struct RealParams {
   double udir[3];      // v / |v| (zero without a velocity)
   double amp_x;        // sqrt(2 dt (D_rw + alpha_l |v|)) - amp: extra amplitude along udir
   int32_t moves;       // 1 if the walk moves particles of this realisation
-  int32_t pad_;
+  // half-stencil tiling: the cell rows are cut into segments of seg_w cells
+  // (seg_w >= 2 * the widest stencil reach), one work item per (row, segment)
+  int32_t seg_w;       // cells per segment
+  int32_t nseg;        // segments per cell row (0: no pair work)
+  int32_t rx_own;      // stencil reach along x on the particle's own row
+  int32_t n_fwd;       // forward stencil rows (dz > 0, or dz = 0 and dy > 0)
+  int64_t item_off;    // first work item of this realisation
 };
 
 // Offset (dy, dz) of a neighbour row of cells and how many cells (rx) to
@@ -75,6 +81,15 @@ struct PairArgs {
   // in the previous sorted order; particle i's are at mass_in[SP * src_of[i]]
   const uint32_t* src_of;  // [cap] previous sorted slot of each sorted particle
   int32_t indirect;
+  // half-stencil tiling: the far-end sums of each work item go to slot planes
+  // [2 * direction + segment parity][cap][V] (V = 1 for the row sums, species
+  // slots for the exchange); each particle's own sums to half_own[cap][V]
+  float* half_slots;
+  double* half_own;
+  const int64_t* half_item_start;  // [n_real + 1] first work item of each realisation
+  int64_t half_nitems;
+  int64_t half_cap;                // particles per slot plane
+  int32_t n_real;
 };
 
 }  // namespace rwpt

@@ -70,6 +70,9 @@ constexpr int kPrivateLists = -1;
 constexpr int kCacheLane = 8;
 constexpr int kCacheWave = 256;
 constexpr uint32_t kCacheMiss = 15;
+// Half-stencil tiling (binary32): every unordered pair evaluated once, its
+// far-end share accumulated into slot planes and summed by a finalizer.
+constexpr int kHalfPairs = -4;
 hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);

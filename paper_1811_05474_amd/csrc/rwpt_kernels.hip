@@ -1777,6 +1777,423 @@ __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ par
 }
 
 // ---------------------------------------------------------------------------
+// Half-stencil tiling (binary32): each unordered pair evaluated once.
+//
+// A work item (one wave) is a segment of seg_w cells of one cell row.  It
+// takes the segment's particles in tiles of 16 (one per lane of each 16-lane
+// DPP row) and, for each tile, only the forward half of the candidates: the
+// later particles of its own row within reach, and the forward stencil rows
+// (dz > 0, or dz = 0 and dy > 0).  Pairs inside a tile are evaluated from
+// both ends (one-sided).  For the other pairs a row's 16 lanes hold the tile's
+// particles and 16 candidates; at step K lane k pairs its particle with the
+// candidate K lanes away (DPP row_ror:K, folded into the subtraction), and
+// the candidate's accumulator travels with it (row_ror:1 folded into the
+// accumulation), so after 16 steps each lane holds, for the candidate it
+// loaded, the sum over the tile's particles.  The particle's own sums stay in
+// its lane.  The candidate sums are added into slot planes indexed by
+// (direction, segment parity): with seg_w >= 2 * the widest reach, at most
+// two segments of a row reach any target cell and they differ in parity, so
+// every slot is written by one wave only, which clears its slots first and
+// then accumulates in program order.  A finalizer adds a particle's own sum
+// and its slots in a fixed order.  No floating-point atomics: the result is
+// bitwise reproducible.
+// ---------------------------------------------------------------------------
+
+// Value of the lane K places along this lane's 16-lane row (row_ror:K).
+template <int K>
+__device__ __forceinline__ float rror(float v) {
+  if constexpr (K == 0) {
+    return v;
+  } else {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x120 + K, 0xf,
+                                                                 0xf, false));
+  }
+}
+
+__device__ __forceinline__ bool forward_row(const StencilRow& sr) { return sr.dz > 0 || (sr.dz == 0 && sr.dy > 0); }
+
+__device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Wave-uniform cursor over the forward candidate ranges of one tile: the own
+// row first (direction 0: particles after the tile up to the reach), then the
+// forward stencil rows in stencil order (directions 1, 2, ... counted whether
+// or not the target row exists, as the finalizers count them).
+struct HalfCursor {
+  int f;            // next stencil entry (-1: the own row is next)
+  int nfwd;         // forward stencil entries seen
+  int dix;          // direction of the current range
+  uint32_t jb, je;  // current range of sorted indices
+  uint32_t p;       // virtual index of jb
+  bool valid;
+};
+
+__device__ __forceinline__ void half_advance(HalfCursor& c, const RealParams& P, const StencilRow* __restrict__ st,
+                                             const uint32_t* __restrict__ cell_start, int y, int z, int64_t rowbase,
+                                             int cxa, int cxb, uint32_t t1) {
+  const int nc0 = P.nc[0], nc1 = P.nc[1], nc2 = P.nc[2];
+  c.valid = false;
+  while (true) {
+    uint32_t jb, je;
+    int dix;
+    if (c.f < 0) {
+      c.f = 0;
+      jb = t1;
+      const int xb = cxb + P.rx_own > nc0 - 1 ? nc0 - 1 : cxb + P.rx_own;
+      je = cell_start[rowbase + xb + 1];
+      dix = 0;
+    } else {
+      if (c.f >= P.n_stencil) return;
+      const StencilRow sr = st[P.stencil_off + c.f];
+      ++c.f;
+      if (!forward_row(sr)) continue;
+      dix = ++c.nfwd;
+      const int ty = y + sr.dy, tz = z + sr.dz;
+      if (ty < 0 || ty >= nc1 || tz < 0 || tz >= nc2) continue;
+      const int64_t cb = P.cell_off + ((int64_t)tz * nc1 + ty) * nc0;
+      const int xa = cxa - sr.rx < 0 ? 0 : cxa - sr.rx;
+      const int xb = cxb + sr.rx > nc0 - 1 ? nc0 - 1 : cxb + sr.rx;
+      jb = cell_start[cb + xa];
+      je = cell_start[cb + xb + 1];
+    }
+    if (je > jb) {
+      c.jb = jb;
+      c.je = je;
+      c.dix = dix;
+      c.valid = true;
+      return;
+    }
+  }
+}
+
+// Lane's candidate of the chunk at virtual index vbase (jdummy, has = false
+// past the last range) and its direction; advances over ranges ending in the
+// chunk.
+__device__ __forceinline__ void half_pick(HalfCursor& c, const RealParams& P, const StencilRow* __restrict__ st,
+                                          const uint32_t* __restrict__ cell_start, int y, int z, int64_t rowbase,
+                                          int cxa, int cxb, uint32_t t1, uint32_t vbase, int32_t jdummy, int32_t& j,
+                                          bool& has, int& dix) {
+  const uint32_t v = vbase + (uint32_t)(threadIdx.x & 63);
+  j = jdummy;
+  has = false;
+  dix = 0;
+  while (c.valid) {
+    const uint32_t len = c.je - c.jb;
+    if (v >= c.p && v < c.p + len) {
+      j = (int32_t)(c.jb + (v - c.p));
+      has = true;
+      dix = c.dix;
+    }
+    if (c.p + len <= vbase + 64) {
+      c.p += len;
+      half_advance(c, P, st, cell_start, y, z, rowbase, cxa, cxb, t1);
+    } else {
+      break;
+    }
+  }
+}
+
+// Realisation of work item w (binary search over the first items).
+__device__ __forceinline__ int half_real(const int64_t* __restrict__ item_start, int n_real, int64_t w) {
+  int lo = 0, hi = n_real - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (item_start[mid] <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One pass of the half-stencil tiling.  EXCH = false: row sums (V = 1, the
+// weight w_ij to both ends); EXCH = true: the exchange (V = SMAX species
+// values: t = w_ij (q_i + q_j)(M_j - M_i) for the symmetric normalisation or
+// w_ij (M_j - M_i) for the row normalisation, +t to i and -t to j).
+template <int DIM, int SMAX, bool EXCH>
+__global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
+  constexpr int V = EXCH ? SMAX : 1;
+  const int lane = threadIdx.x & 63;
+  const int gi = lane & 15, gl = lane >> 4;
+  const int64_t w = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
+                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (w >= a.half_nitems) return;
+  const int r = __builtin_amdgcn_readfirstlane(half_real(a.half_item_start, a.n_real, w));
+  const RealParams& P = a.rp[r];
+  if (!P.active || P.nseg <= 0) return;
+  const float* __restrict__ pos = (const float*)a.pos;
+  const float* __restrict__ min_ = (const float*)a.mass_in;
+  const float* __restrict__ q = (const float*)a.q_in;
+  float* __restrict__ slots = a.half_slots;
+  const int64_t cap = a.half_cap;
+  const int nc0 = P.nc[0], nc1 = P.nc[1], nc2 = P.nc[2];
+  const int W = P.seg_w;
+  const int64_t li = w - a.half_item_start[r];
+  const int row = (int)(li / P.nseg), sg = (int)(li % P.nseg);
+  const int y = row % nc1, z = row / nc1;
+  const int64_t rowbase = P.cell_off + (int64_t)row * nc0;
+  const int c0 = sg * W, c1 = ((sg + 1) * W < nc0 ? (sg + 1) * W : nc0) - 1;
+  const int par = sg & 1;
+  const uint32_t* __restrict__ cs = a.cell_start;
+
+  // clear this item's slots: one window per direction, on the target row
+  auto clear = [&](int dix, int64_t cb, int xa, int xb) {
+    const uint32_t wb = cs[cb + xa], we = cs[cb + xb + 1];
+    float* __restrict__ plane = slots + (int64_t)(2 * dix + par) * cap * V;
+    for (uint32_t j = wb + lane; j < we; j += 64) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) plane[(int64_t)j * V + v] = 0.0f;
+    }
+  };
+  clear(0, rowbase, c0, c1 + P.rx_own > nc0 - 1 ? nc0 - 1 : c1 + P.rx_own);
+  {
+    int nf = 0;
+    for (int f = 0; f < P.n_stencil; ++f) {
+      const StencilRow sr = a.st[P.stencil_off + f];
+      if (!forward_row(sr)) continue;
+      ++nf;
+      const int ty = y + sr.dy, tz = z + sr.dz;
+      if (ty < 0 || ty >= nc1 || tz < 0 || tz >= nc2) continue;
+      clear(nf, P.cell_off + ((int64_t)tz * nc1 + ty) * nc0, c0 - sr.rx < 0 ? 0 : c0 - sr.rx,
+            c1 + sr.rx > nc0 - 1 ? nc0 - 1 : c1 + sr.rx);
+    }
+  }
+
+  const uint32_t pb = cs[rowbase + c0], pe = cs[rowbase + c1 + 1];
+  const float rc2 = P.rc2_f, esc = P.escale_f;
+  const bool sym = a.norm == 0;
+  for (uint32_t t0 = pb; t0 < pe; t0 += 16) {
+    const uint32_t t1 = t0 + 16 < pe ? t0 + 16 : pe;
+    const int n_in = (int)(t1 - t0);
+    const bool valid = gi < n_in;
+    const int32_t ii = valid ? (int32_t)t0 + gi : (int32_t)t1 - 1;
+    float xi[DIM];
+    load_pos<float, DIM>(pos, ii, xi);
+    // a lane past the tile's end: its separations overflow to +inf, weight 0
+    if (!valid) xi[0] = -3.0e38f;
+    float qi = 0.0f, Mi[SMAX];
+#pragma unroll
+    for (int v = 0; v < SMAX; ++v) Mi[v] = 0.0f;
+    if constexpr (EXCH) {
+      qi = q[ii];
+      load_mass<float, SMAX>(min_, ii, Mi);
+    }
+    const int cxa = (int)(a.skey[t0] - (uint32_t)rowbase);
+    const int cxb = (int)(a.skey[t1 - 1] - (uint32_t)rowbase);
+    double acc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = 0.0;
+
+    // pairs inside the tile, from both ends: row g takes the rotations
+    // 4g .. 4g + 3 of the tile's particles (all 16 over the four rows; the
+    // rotation 0 is the particle itself, weight 1)
+    {
+      float part[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) part[v] = 0.0f;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int src = (lane & 48) | ((gi + 4 * gl + kk) & 15);
+        float s2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          const float dk = __shfl(xi[k], src) - xi[k];
+          s2 = k == 0 ? dk * dk : __builtin_fmaf(dk, dk, s2);
+        }
+        float wgt = kweight(s2, esc);
+        wgt = s2 <= rc2 ? wgt : 0.0f;
+        if constexpr (EXCH) {
+          const float pp = sym ? wgt * (__shfl(qi, src) + qi) : wgt;
+#pragma unroll
+          for (int v = 0; v < SMAX; ++v) part[v] += pp * (__shfl(Mi[v], src) - Mi[v]);
+        } else {
+          part[0] += wgt;
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] += (double)part[v];
+    }
+
+    // forward candidates, 64 per chunk, the next chunk's loads issued before
+    // the current chunk is computed
+    struct Cand {
+      float x[DIM], m[SMAX], q;
+      int32_t j;
+      int dix;
+      bool has;
+    };
+    auto load = [&](int32_t j, bool has, int dix) {
+      Cand d;
+      load_pos<float, DIM>(pos, j, d.x);
+      if (!has) d.x[0] = 3.0e38f;  // a dummy candidate: separation +inf, weight 0
+      if constexpr (EXCH) {
+        d.q = q[j];
+        load_mass<float, SMAX>(min_, j, d.m);
+      } else {
+        d.q = 0.0f;
+#pragma unroll
+        for (int v = 0; v < SMAX; ++v) d.m[v] = 0.0f;
+      }
+      d.j = j;
+      d.dix = dix;
+      d.has = has;
+      return d;
+    };
+    auto compute = [&](const Cand& d) {
+      float ai[V], aj[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        ai[v] = 0.0f;
+        aj[v] = 0.0f;
+      }
+      // every DPP operand below is read with all lanes active
+      Steps<0, 16>::run([&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        float s2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          const float dk = rror<K>(d.x[k]) - xi[k];
+          s2 = k == 0 ? dk * dk : __builtin_fmaf(dk, dk, s2);
+        }
+        float wgt = kweight(s2, esc);
+        wgt = s2 <= rc2 ? wgt : 0.0f;
+        if constexpr (EXCH) {
+          const float pp = sym ? wgt * (rror<K>(d.q) + qi) : wgt;
+#pragma unroll
+          for (int v = 0; v < SMAX; ++v) {
+            const float t = pp * (rror<K>(d.m[v]) - Mi[v]);
+            ai[v] += t;
+            aj[v] = (K == 0 ? 0.0f : rror<1>(aj[v])) - t;
+          }
+        } else {
+          ai[0] += wgt;
+          aj[0] = (K == 0 ? 0.0f : rror<1>(aj[0])) + wgt;
+        }
+      });
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        acc[v] += (double)ai[v];
+        aj[v] = rror<1>(aj[v]);  // the sum of this lane's own candidate
+      }
+      if (d.has) {
+        float* __restrict__ sl = slots + ((int64_t)(2 * d.dix + par) * cap + d.j) * V;
+#pragma unroll
+        for (int v = 0; v < V; ++v) sl[v] += aj[v];
+      }
+    };
+    HalfCursor c;
+    c.f = -1;
+    c.nfwd = 0;
+    c.p = 0;
+    half_advance(c, P, a.st, cs, y, z, rowbase, cxa, cxb, t1);
+    if (c.valid) {
+      uint32_t vbase = 0;
+      int32_t j;
+      bool has;
+      int dix;
+      half_pick(c, P, a.st, cs, y, z, rowbase, cxa, cxb, t1, vbase, (int32_t)t0, j, has, dix);
+      Cand cur = load(j, has, dix);
+      while (true) {
+        const bool next = c.valid;
+        Cand nxt = cur;
+        if (next) {
+          vbase += 64;
+          half_pick(c, P, a.st, cs, y, z, rowbase, cxa, cxb, t1, vbase, (int32_t)t0, j, has, dix);
+          nxt = load(j, has, dix);
+        }
+        compute(cur);
+        if (!next) break;
+        cur = nxt;
+      }
+    }
+    // the particle's own sums over the four rows
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      acc[v] += __shfl_xor(acc[v], 16);
+      acc[v] += __shfl_xor(acc[v], 32);
+    }
+    if (gl == 0 && valid) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) a.half_own[(int64_t)ii * V + v] = acc[v];
+    }
+  }
+}
+
+// Sum of particle i's slots of V values: for each direction in order (own row
+// first, then the forward stencil rows whose source row exists) the one or
+// two segments of the source row whose windows reach i's cell, ascending.
+template <int V>
+__device__ __forceinline__ void half_gather(const PairArgs& a, const RealParams& P, int32_t i, double (&acc)[V]) {
+  const uint32_t lk = a.skey[i] - (uint32_t)P.cell_off;
+  const int nc0 = P.nc[0], nc1 = P.nc[1], nc2 = P.nc[2];
+  const int cx = (int)(lk % (uint32_t)nc0);
+  const int rowi = (int)(lk / (uint32_t)nc0);
+  const int y = rowi % nc1, z = rowi / nc1;
+  const int W = P.seg_w, nseg = P.nseg;
+  const float* __restrict__ slots = a.half_slots;
+  const int64_t cap = a.half_cap;
+  auto add = [&](int dix, int rx, bool own) {
+    int slo = floordiv(cx - rx, W), shi = own ? cx / W : floordiv(cx + rx, W);
+    slo = slo < 0 ? 0 : slo;
+    shi = shi > nseg - 1 ? nseg - 1 : shi;
+    for (int sg = slo; sg <= shi; ++sg) {
+      const float* __restrict__ sl = slots + ((int64_t)(2 * dix + (sg & 1)) * cap + i) * V;
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] += (double)sl[v];
+    }
+  };
+  add(0, P.rx_own, true);
+  int nf = 0;
+  for (int f = 0; f < P.n_stencil; ++f) {
+    const StencilRow sr = a.st[P.stencil_off + f];
+    if (!forward_row(sr)) continue;
+    ++nf;
+    const int sy = y - sr.dy, sz = z - sr.dz;
+    if (sy < 0 || sy >= nc1 || sz < 0 || sz >= nc2) continue;
+    add(nf, sr.rx, false);
+  }
+}
+
+// Row sums of the half-stencil tiling: r_i = own sum + slots; q_i = 1 / r_i.
+__global__ __launch_bounds__(kBlock) void k_half_rowsum_fin(PairArgs a) {
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<0>(a.tiles, a.ntiles, tl, tile)) return;
+  if (!tl.valid) return;
+  const RealParams& P = a.rp[tile.real];
+  double r[1] = {1.0};
+  if (P.active && P.nseg > 0) {
+    r[0] = a.half_own[tl.i];
+    half_gather<1>(a, P, tl.i, r);
+  }
+  a.r_out[tl.i] = r[0];
+  ((float*)a.q_out)[tl.i] = (float)(1.0 / r[0]);
+}
+
+// Exchange of the half-stencil tiling: the particle's sums of t over its
+// neighbours (own sums + slots), then the explicit update, the reaction and
+// the audit partials of the one-lane-per-particle tiles.
+template <int SMAX>
+__global__ __launch_bounds__(kBlock) void k_half_exchange_fin(PairArgs a) {
+  TileLane tl;
+  Tile tile;
+  if (!tile_lane_setup<0>(a.tiles, a.ntiles, tl, tile)) return;
+  const RealParams& P = a.rp[tile.real];
+  const int32_t ii = tl.valid ? tl.i : tile.end - 1;
+  float Mi[SMAX];
+  load_mass<float, SMAX>((const float*)a.mass_in, ii, Mi);
+  double acc[SMAX];
+#pragma unroll
+  for (int v = 0; v < SMAX; ++v) acc[v] = 0.0;
+  double racc = 1.0;
+  if (tl.valid && P.active && P.nseg > 0) {
+#pragma unroll
+    for (int v = 0; v < SMAX; ++v) acc[v] = a.half_own[(int64_t)ii * SMAX + v];
+    half_gather<SMAX>(a, P, ii, acc);
+    racc = a.r_out[ii];
+  }
+  exchange_epilogue<float, SMAX, 64>(P, a.norm == 0, acc, racc, Mi, tl.valid, tl.i, (float*)a.mass_out, a.S,
+                                     a.react_a, a.react_b, a.audit_part, wave_tile());
+}
+
+// ---------------------------------------------------------------------------
 // Allocation-free transfer of one realisation held in caller arrays: set-up
 // kernels that write the step's parameters, stencil, tiles and cleared cell
 // counts from kernel arguments, convert the caller's layouts, and return the
@@ -1970,8 +2387,40 @@ static hipError_t dispatch_tdl(int fp64, int dim, int log2l, F&& f) {
   return fp64 ? with_d(double{}) : with_d(float{});
 }
 
+static hipError_t launch_half(int dim, bool exch, const PairArgs& a, hipStream_t s) {
+  if (a.half_nitems > 0) {
+    const dim3 g((unsigned)((a.half_nitems + kBlock / 64 - 1) / (kBlock / 64))), b(kBlock);
+    auto go = [&](auto d, auto sm) {
+      constexpr int D = decltype(d)::value, SM = decltype(sm)::value;
+      if (exch) hipLaunchKernelGGL((k_half_pairs<D, SM, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_half_pairs<D, SM, false>), g, b, 0, s, a);
+    };
+    auto go_s = [&](auto d) {
+      if (!exch || a.S <= 2) go(d, IC<2>{});
+      else if (a.S <= 4) go(d, IC<4>{});
+      else go(d, IC<8>{});
+    };
+    if (dim == 1) go_s(IC<1>{});
+    else if (dim == 2) go_s(IC<2>{});
+    else if (dim == 3) go_s(IC<3>{});
+    else return hipErrorInvalidValue;
+  }
+  const dim3 g = pair_grid(a.ntiles), b(kBlock);
+  if (!exch) {
+    hipLaunchKernelGGL(k_half_rowsum_fin, g, b, 0, s, a);
+  } else if (a.S <= 2) {
+    hipLaunchKernelGGL(k_half_exchange_fin<2>, g, b, 0, s, a);
+  } else if (a.S <= 4) {
+    hipLaunchKernelGGL(k_half_exchange_fin<4>, g, b, 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_half_exchange_fin<8>, g, b, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
+  if (log2l == kHalfPairs) return fp64 ? hipErrorInvalidValue : launch_half(dim, false, a, s);
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
   if (log2l == kPrivateLists) {
     return dispatch_tdl(fp64, dim, 0, [&](auto t, auto d, auto) {
@@ -2012,6 +2461,7 @@ hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStr
 hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   if (a.S < 1 || a.S > 8) return hipErrorInvalidValue;
+  if (log2l == kHalfPairs) return fp64 ? hipErrorInvalidValue : launch_half(dim, true, a, s);
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
   if (log2l == kPrivateLists) {
     return dispatch_tdl(fp64, dim, 0, [&](auto t, auto d, auto) {
@@ -2092,6 +2542,7 @@ static hipError_t launch_nbr_dpp(int dim, const PairArgs& a, hipStream_t s) {
 
 hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
+  if (log2l == kHalfPairs) log2l = 0;  // same tiles of 64 particles
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
   if (log2l == kPrivateLists) {  // same tiles of 64, one lane per particle
     return dispatch_tdl(fp64, dim, 0, [&](auto t, auto d, auto) {
@@ -2112,6 +2563,7 @@ hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStre
 template <bool FILL>
 static hipError_t launch_nbr(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
+  if (log2l == kHalfPairs) log2l = 0;  // same tiles of 64 particles
   const dim3 g = pair_grid(a.ntiles), b(kBlock);
   if (log2l == kPrivateLists) {
     return dispatch_tdl(fp64, dim, 0, [&](auto t, auto d, auto) {
