@@ -378,18 +378,33 @@ static void real_grid(const rwpt_config& cfg, int dim, double dt, double Dr, int
   P.n_stencil = (int32_t)st.size() - P.stencil_off;
 }
 
-// Segments of the half-stencil tiling for one realisation: seg_w = twice the
-// widest reach along x of its stencil rows (so at most two segments of a row,
-// of different parity, reach any cell), the own row's reach, and the number
-// of forward stencil rows (dz > 0, or dz = 0 and dy > 0).
-static void half_segments(RealParams& P, const StencilRow* st) {
+// Segments of the half-stencil tiling for one realisation: seg_w =
+// ceil(2 * the widest reach along x of its stencil rows / (npar - 1)), so that
+// at most npar consecutive segments of a row (distinct mod npar) reach any
+// cell; the own row's reach; the number of forward stencil rows (dz > 0, or
+// dz = 0 and dy > 0).
+static void half_segments(RealParams& P, const StencilRow* st, int64_t nr, int64_t target) {
   int rx_max = 0, rx_own = 0, n_fwd = 0;
   for (int f = 0; f < P.n_stencil; ++f) {
     rx_max = std::max(rx_max, st[f].rx);
     if (st[f].dy == 0 && st[f].dz == 0) rx_own = st[f].rx;
     if (st[f].dz > 0 || (st[f].dz == 0 && st[f].dy > 0)) ++n_fwd;
   }
-  P.seg_w = std::max(1, 2 * rx_max);
+  P.npar = kHalfParities;
+  P.seg_w = std::max(1, (2 * rx_max + P.npar - 2) / (P.npar - 1));
+  // wider segments where neighbourhoods are sparse, so that a work item has
+  // about `target` candidate evaluations on average (any width above the
+  // bound keeps the slots single-writer): candidates per particle ~ particles
+  // per cell x cells of the stencil
+  const int64_t cells = (int64_t)P.nc[0] * P.nc[1] * P.nc[2];
+  if (nr > 0 && cells > 0) {
+    int64_t stencil_cells = 0;
+    for (int f = 0; f < P.n_stencil; ++f) stencil_cells += 2 * st[f].rx + 1;
+    const double per_cell = (double)nr / (double)cells;
+    const double cand = std::max(1.0, per_cell * (double)stencil_cells);
+    const double want = std::ceil((double)target / cand / per_cell);
+    if (want > (double)P.seg_w) P.seg_w = (int32_t)std::min<double>(want, (double)P.nc[0]);
+  }
   P.nseg = P.active ? (P.nc[0] + P.seg_w - 1) / P.seg_w : 0;
   P.rx_own = rx_own;
   P.n_fwd = n_fwd;
@@ -421,7 +436,7 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
     P.p_begin = c->real_start[r];
     P.p_end = c->real_start[r + 1];
     cell_off += (int64_t)P.nc[0] * P.nc[1] * P.nc[2];
-    if (half) half_segments(P, c->h_st.data() + P.stencil_off);
+    if (half) half_segments(P, c->h_st.data() + P.stencil_off, nr, kHalfTarget);
     c->h_tile_start[r] = (int32_t)c->h_tiles.size();
     for (int64_t b = P.p_begin; b < P.p_end; b += G)
       c->h_tiles.push_back(Tile{(int32_t)b, (int32_t)std::min<int64_t>(b + G, P.p_end), r, 0});
@@ -440,7 +455,7 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   if (cell_off >= (int64_t)1 << 31) return fail(c, RWPT_EUNSUPPORTED, "cell grid too large (%lld cells)", (long long)cell_off);
   c->ntiles = (int32_t)c->h_tiles.size();
   // half-stencil tiling: work items (row, segment) of every realisation, and
-  // slot planes 2 (1 + forward rows) deep
+  // slot planes npar (1 + forward rows) deep
   std::vector<int64_t> item_start(c->n_real + 1, 0);
   int max_fwd = 0;
   c->half_nitems = 0;
@@ -476,7 +491,7 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   }
   if (half) {
     const int Sa = padded_species(c->S);
-    HIPCHK(c, c->half_slots.ensure((size_t)2 * (1 + max_fwd) * c->cap * Sa * sizeof(float)));
+    HIPCHK(c, c->half_slots.ensure((size_t)kHalfParities * (1 + max_fwd) * c->cap * Sa * sizeof(float)));
     HIPCHK(c, c->half_own.ensure((size_t)c->cap * Sa * sizeof(double)));
     HIPCHK(c, c->d_item_start.ensure(item_start.size() * sizeof(int64_t)));
     HIPCHK(c, hipMemcpyAsync(c->d_item_start.p, item_start.data(), item_start.size() * sizeof(int64_t),

@@ -28,10 +28,12 @@ struct RealParams {
   double udir[3];      // v / |v| (zero without a velocity)
   double amp_x;        // sqrt(2 dt (D_rw + alpha_l |v|)) - amp: extra amplitude along udir
   int32_t moves;       // 1 if the walk moves particles of this realisation
-  // half-stencil tiling: the cell rows are cut into segments of seg_w cells
-  // (seg_w >= 2 * the widest stencil reach), one work item per (row, segment)
+  // half-stencil tiling: the cell rows are cut into segments of seg_w cells,
+  // seg_w >= 2 * the widest stencil reach / (npar - 1), one work item per
+  // (row, segment); at most npar consecutive segments reach a cell
   int32_t seg_w;       // cells per segment
   int32_t nseg;        // segments per cell row (0: no pair work)
+  int32_t npar;        // slot planes per direction (segment index mod npar)
   int32_t rx_own;      // stencil reach along x on the particle's own row
   int32_t n_fwd;       // forward stencil rows (dz > 0, or dz = 0 and dy > 0)
   int64_t item_off;    // first work item of this realisation
@@ -82,8 +84,9 @@ struct PairArgs {
   const uint32_t* src_of;  // [cap] previous sorted slot of each sorted particle
   int32_t indirect;
   // half-stencil tiling: the far-end sums of each work item go to slot planes
-  // [2 * direction + segment parity][cap][V] (V = 1 for the row sums, species
-  // slots for the exchange); each particle's own sums to half_own[cap][V]
+  // [npar * direction + segment mod npar][cap][V] (V = 1 for the row sums,
+  // species slots for the exchange); each particle's own sums to
+  // half_own[cap][V]
   float* half_slots;
   double* half_own;
   const int64_t* half_item_start;  // [n_real + 1] first work item of each realisation

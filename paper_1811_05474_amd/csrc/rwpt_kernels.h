@@ -73,6 +73,13 @@ constexpr uint32_t kCacheMiss = 15;
 // Half-stencil tiling (binary32): every unordered pair evaluated once, its
 // far-end share accumulated into slot planes and summed by a finalizer.
 constexpr int kHalfPairs = -4;
+// Slot planes per direction of the half-stencil tiling: segments of
+// ceil(2 * reach / (kHalfParities - 1)) cells, so that a cell row of a
+// realisation gives enough work items to fill the device.
+constexpr int kHalfParities = 2;
+// Candidate evaluations per work item of the half-stencil tiling aimed at on
+// average (segments are widened up to this where neighbourhoods are sparse).
+constexpr int64_t kHalfTarget = 32768;
 hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);

@@ -1791,10 +1791,10 @@ __global__ __launch_bounds__(kBlock) void k_audit(const double* __restrict__ par
 // accumulation), so after 16 steps each lane holds, for the candidate it
 // loaded, the sum over the tile's particles.  The particle's own sums stay in
 // its lane.  The candidate sums are added into slot planes indexed by
-// (direction, segment parity): with seg_w >= 2 * the widest reach, at most
-// two segments of a row reach any target cell and they differ in parity, so
-// every slot is written by one wave only, which clears its slots first and
-// then accumulates in program order.  A finalizer adds a particle's own sum
+// (direction, segment index mod npar): with seg_w >= 2 * the widest reach /
+// (npar - 1), at most npar consecutive segments of a row reach any target
+// cell, so every slot is written by one wave only, which clears its slots
+// first and then accumulates in program order.  A finalizer adds a particle's own sum
 // and its slots in a fixed order.  No floating-point atomics: the result is
 // bitwise reproducible.
 // ---------------------------------------------------------------------------
@@ -1805,8 +1805,10 @@ __device__ __forceinline__ float rror(float v) {
   if constexpr (K == 0) {
     return v;
   } else {
+    // every source lane of a row rotation exists; bound_ctrl lets the
+    // compiler fold the read into the consuming instruction
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x120 + K, 0xf,
-                                                                 0xf, false));
+                                                                 0xf, true));
   }
 }
 
@@ -1907,7 +1909,7 @@ __device__ __forceinline__ int half_real(const int64_t* __restrict__ item_start,
 // weight w_ij to both ends); EXCH = true: the exchange (V = SMAX species
 // values: t = w_ij (q_i + q_j)(M_j - M_i) for the symmetric normalisation or
 // w_ij (M_j - M_i) for the row normalisation, +t to i and -t to j).
-template <int DIM, int SMAX, bool EXCH>
+template <int DIM, int SMAX, bool EXCH, bool SYM>
 __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
   constexpr int V = EXCH ? SMAX : 1;
   const int lane = threadIdx.x & 63;
@@ -1930,13 +1932,13 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
   const int y = row % nc1, z = row / nc1;
   const int64_t rowbase = P.cell_off + (int64_t)row * nc0;
   const int c0 = sg * W, c1 = ((sg + 1) * W < nc0 ? (sg + 1) * W : nc0) - 1;
-  const int par = sg & 1;
+  const int npar = P.npar, par = sg % npar;
   const uint32_t* __restrict__ cs = a.cell_start;
 
   // clear this item's slots: one window per direction, on the target row
   auto clear = [&](int dix, int64_t cb, int xa, int xb) {
     const uint32_t wb = cs[cb + xa], we = cs[cb + xb + 1];
-    float* __restrict__ plane = slots + (int64_t)(2 * dix + par) * cap * V;
+    float* __restrict__ plane = slots + (int64_t)(npar * dix + par) * cap * V;
     for (uint32_t j = wb + lane; j < we; j += 64) {
 #pragma unroll
       for (int v = 0; v < V; ++v) plane[(int64_t)j * V + v] = 0.0f;
@@ -1958,7 +1960,6 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
 
   const uint32_t pb = cs[rowbase + c0], pe = cs[rowbase + c1 + 1];
   const float rc2 = P.rc2_f, esc = P.escale_f;
-  const bool sym = a.norm == 0;
   for (uint32_t t0 = pb; t0 < pe; t0 += 16) {
     const uint32_t t1 = t0 + 16 < pe ? t0 + 16 : pe;
     const int n_in = (int)(t1 - t0);
@@ -2000,7 +2001,7 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
         float wgt = kweight(s2, esc);
         wgt = s2 <= rc2 ? wgt : 0.0f;
         if constexpr (EXCH) {
-          const float pp = sym ? wgt * (__shfl(qi, src) + qi) : wgt;
+          const float pp = SYM ? wgt * (__shfl(qi, src) + qi) : wgt;
 #pragma unroll
           for (int v = 0; v < SMAX; ++v) part[v] += pp * (__shfl(Mi[v], src) - Mi[v]);
         } else {
@@ -2015,12 +2016,18 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
     // the current chunk is computed
     struct Cand {
       float x[DIM], m[SMAX], q;
+      float sl[V];  // the candidate's slot, read ahead (no other chunk of this tile touches it)
       int32_t j;
       int dix;
       bool has;
     };
     auto load = [&](int32_t j, bool has, int dix) {
       Cand d;
+      {
+        const float* __restrict__ sp = slots + ((int64_t)(npar * dix + par) * cap + (has ? j : 0)) * V;
+#pragma unroll
+        for (int v = 0; v < V; ++v) d.sl[v] = has ? sp[v] : 0.0f;
+      }
       load_pos<float, DIM>(pos, j, d.x);
       if (!has) d.x[0] = 3.0e38f;  // a dummy candidate: separation +inf, weight 0
       if constexpr (EXCH) {
@@ -2043,8 +2050,10 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
         ai[v] = 0.0f;
         aj[v] = 0.0f;
       }
-      // every DPP operand below is read with all lanes active
+      // every DPP operand below is read with all lanes active; no
+      // contraction, so that the rotations fold into the adds and subtracts
       Steps<0, 16>::run([&](auto kc) {
+#pragma clang fp contract(off)
         constexpr int K = decltype(kc)::value;
         float s2 = 0.0f;
 #pragma unroll
@@ -2055,16 +2064,16 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
         float wgt = kweight(s2, esc);
         wgt = s2 <= rc2 ? wgt : 0.0f;
         if constexpr (EXCH) {
-          const float pp = sym ? wgt * (rror<K>(d.q) + qi) : wgt;
+          const float pp = SYM ? wgt * (rror<K>(d.q) + qi) : wgt;
 #pragma unroll
           for (int v = 0; v < SMAX; ++v) {
             const float t = pp * (rror<K>(d.m[v]) - Mi[v]);
             ai[v] += t;
-            aj[v] = (K == 0 ? 0.0f : rror<1>(aj[v])) - t;
+            aj[v] = (K == 0 ? -t : rror<1>(aj[v]) - t);
           }
         } else {
           ai[0] += wgt;
-          aj[0] = (K == 0 ? 0.0f : rror<1>(aj[0])) + wgt;
+          aj[0] = (K == 0 ? wgt : rror<1>(aj[0]) + wgt);
         }
       });
 #pragma unroll
@@ -2073,9 +2082,9 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
         aj[v] = rror<1>(aj[v]);  // the sum of this lane's own candidate
       }
       if (d.has) {
-        float* __restrict__ sl = slots + ((int64_t)(2 * d.dix + par) * cap + d.j) * V;
+        float* __restrict__ sl = slots + ((int64_t)(npar * d.dix + par) * cap + d.j) * V;
 #pragma unroll
-        for (int v = 0; v < V; ++v) sl[v] += aj[v];
+        for (int v = 0; v < V; ++v) sl[v] = d.sl[v] + aj[v];
       }
     };
     HalfCursor c;
@@ -2117,8 +2126,8 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
 }
 
 // Sum of particle i's slots of V values: for each direction in order (own row
-// first, then the forward stencil rows whose source row exists) the one or
-// two segments of the source row whose windows reach i's cell, ascending.
+// first, then the forward stencil rows whose source row exists) the segments
+// of the source row whose windows reach i's cell (at most npar), ascending.
 template <int V>
 __device__ __forceinline__ void half_gather(const PairArgs& a, const RealParams& P, int32_t i, double (&acc)[V]) {
   const uint32_t lk = a.skey[i] - (uint32_t)P.cell_off;
@@ -2126,7 +2135,7 @@ __device__ __forceinline__ void half_gather(const PairArgs& a, const RealParams&
   const int cx = (int)(lk % (uint32_t)nc0);
   const int rowi = (int)(lk / (uint32_t)nc0);
   const int y = rowi % nc1, z = rowi / nc1;
-  const int W = P.seg_w, nseg = P.nseg;
+  const int W = P.seg_w, nseg = P.nseg, npar = P.npar;
   const float* __restrict__ slots = a.half_slots;
   const int64_t cap = a.half_cap;
   auto add = [&](int dix, int rx, bool own) {
@@ -2134,7 +2143,7 @@ __device__ __forceinline__ void half_gather(const PairArgs& a, const RealParams&
     slo = slo < 0 ? 0 : slo;
     shi = shi > nseg - 1 ? nseg - 1 : shi;
     for (int sg = slo; sg <= shi; ++sg) {
-      const float* __restrict__ sl = slots + ((int64_t)(2 * dix + (sg & 1)) * cap + i) * V;
+      const float* __restrict__ sl = slots + ((int64_t)(npar * dix + sg % npar) * cap + i) * V;
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[v] += (double)sl[v];
     }
@@ -2392,8 +2401,9 @@ static hipError_t launch_half(int dim, bool exch, const PairArgs& a, hipStream_t
     const dim3 g((unsigned)((a.half_nitems + kBlock / 64 - 1) / (kBlock / 64))), b(kBlock);
     auto go = [&](auto d, auto sm) {
       constexpr int D = decltype(d)::value, SM = decltype(sm)::value;
-      if (exch) hipLaunchKernelGGL((k_half_pairs<D, SM, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_half_pairs<D, SM, false>), g, b, 0, s, a);
+      if (!exch) hipLaunchKernelGGL((k_half_pairs<D, SM, false, true>), g, b, 0, s, a);
+      else if (a.norm == 0) hipLaunchKernelGGL((k_half_pairs<D, SM, true, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_half_pairs<D, SM, true, false>), g, b, 0, s, a);
     };
     auto go_s = [&](auto d) {
       if (!exch || a.S <= 2) go(d, IC<2>{});
