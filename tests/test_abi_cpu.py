@@ -48,7 +48,7 @@ def test_config_struct_matches_c_layout(lib):
 @pytest.mark.parametrize("field,value", [
     ("dim", 0), ("dim", 4), ("n_species", 0), ("n_species", 9), ("react_a", 5), ("kappa", 0.0),
     ("kappa", -1.0), ("kappa", float("nan")), ("rw_ratio", -1.0), ("precision", 2), ("norm", 3),
-    ("path", 7), ("tile_lanes", 3), ("tile_lanes", 32), ("tile_lanes", -2), ("device", -1), ("use_graph", 2),
+    ("path", 7), ("tile_lanes", 3), ("tile_lanes", 32), ("tile_lanes", -3), ("tile_lanes", 2), ("device", -1), ("use_graph", 2),
     ("alpha_t", -0.1), ("alpha_l", float("nan")),
 ])
 def test_create_rejects_bad_config(lib, field, value):
@@ -239,3 +239,46 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "refused:" in r.stdout and "not built" in r.stdout
+
+
+def test_half_stencil_tiling_is_binary32_only(lib):
+    cfg = rwpt.rwpt_config_default()
+    cfg.tile_lanes = -2
+    ctx = rwpt.rwpt_create(cfg)  # binary32: accepted, no device touched
+    rwpt.rwpt_destroy(ctx)
+    cfg.precision = rwpt.RWPT_FP64
+    with pytest.raises(rwpt.RwptError) as ei:
+        rwpt.rwpt_create(cfg)
+    assert ei.value.status == rwpt.RWPT_EUNSUPPORTED
+
+
+def test_noalloc_validates_before_any_device_work(lib):
+    # every refusal below happens on the host, before the scratch area is
+    # looked up or a kernel is queued (the pointers are never dereferenced)
+    cfg = rwpt.rwpt_config_default()
+    bad = [dict(n=-1), dict(dt=0.0), dict(D=-1.0), dict(D=float("nan")), dict(pos=0), dict(m_out=2)]
+    for kw in bad:
+        args = dict(n=10, pos=1, m_in=2, m_out=3, dt=0.1, D=1e-4)
+        args.update(kw)
+        with pytest.raises(rwpt.RwptError) as ei:
+            rwpt.rwpt_transfer_noalloc(cfg, args["n"], args["pos"], args["m_in"], args["m_out"], args["dt"],
+                                       args["D"])
+        assert ei.value.status == rwpt.RWPT_EINVAL, kw
+    cfg.path = rwpt.RWPT_PATH_DENSE
+    cfg.kappa = math.inf
+    with pytest.raises(rwpt.RwptError) as ei:
+        rwpt.rwpt_transfer_noalloc(cfg, 10, 1, 2, 3, 0.1, 1e-4)
+    assert ei.value.status == rwpt.RWPT_EUNSUPPORTED
+    cfg = rwpt.rwpt_config_default()
+    cfg.tile_lanes = -2
+    with pytest.raises(rwpt.RwptError) as ei:
+        rwpt.rwpt_transfer_noalloc(cfg, 10, 1, 2, 3, 0.1, 1e-4)
+    assert ei.value.status == rwpt.RWPT_EUNSUPPORTED
+    # beyond the fixed scratch area: refused with the size in the message
+    cfg = rwpt.rwpt_config_default()
+    cfg.dim, cfg.n_species, cfg.precision = 3, 8, rwpt.RWPT_FP64
+    with pytest.raises(rwpt.RwptError) as ei:
+        rwpt.rwpt_transfer_noalloc(cfg, 1_000_000, 1, 2, 3, 0.1, 1e-6)
+    assert ei.value.status == rwpt.RWPT_EUNSUPPORTED and "scratch" in str(ei.value)
+    # n = 0 is a no-op
+    rwpt.rwpt_transfer_noalloc(rwpt.rwpt_config_default(), 0, 0, 0, 0, 0.1, 1e-4)
