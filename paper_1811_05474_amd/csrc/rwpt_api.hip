@@ -547,7 +547,7 @@ static PairArgs pair_args(rwpt_ctx* c) {
   a.mass_out = mass_buf(c, c->mcur ^ 1).p;
   a.q_in = c->q.p;
   a.q_out = c->q.p;
-  a.r_out = c->r.as<double>();
+  a.r_out = c->cfg.norm == RWPT_NORM_ROW ? c->r.as<double>() : nullptr;  // read by the exchange
   a.skey = c->skey.as<uint32_t>();
   a.cell_start = c->cell_start.as<uint32_t>();
   a.tiles = c->d_tiles.as<Tile>();
@@ -1266,6 +1266,7 @@ rwpt_status rwpt_debug_rowsums(rwpt_ctx* c, double dt, double D, int32_t unit_we
   st = ensure_sorted(c);
   if (st != RWPT_OK) return st;
   PairArgs a = pair_args(c);
+  a.r_out = c->r.as<double>();
   DevBuf rp_unit;
   rwpt_status result = RWPT_OK;
   do {

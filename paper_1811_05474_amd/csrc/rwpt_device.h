@@ -58,7 +58,8 @@ struct PairArgs {
   void* mass_out;          // [cap][SP]
   const void* q_in;        // 1 / r_i for the symmetric normalisation, [cap]
   void* q_out;             // written by the row-sum pass
-  double* r_out;           // r_i = sum_j w_ij, written by the row-sum pass
+  double* r_out;           // r_i = sum_j w_ij, written by the row-sum pass (null: not kept; the
+                           // symmetric normalisation needs only q)
   const uint32_t* skey;    // global cell key of each sorted particle
   const uint32_t* cell_start;
   const Tile* tiles;

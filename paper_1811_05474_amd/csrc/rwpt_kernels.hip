@@ -671,7 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum(
   for (int off = G; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
   if (tl.gl == 0 && tl.valid) {
     if (!P.active) acc = 1.0;
-    r_out[tl.i] = acc;
+    if (r_out) r_out[tl.i] = acc;
     q_out[tl.i] = (T)(1.0 / acc);
   }
 }
@@ -992,7 +992,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
   acc += __shfl_xor(acc, 32);
   if (tl.gl == 0 && tl.valid) {
     if (!P.active) acc = 1.0;
-    r_out[tl.i] = acc;
+    if (r_out) r_out[tl.i] = acc;
     q_out[tl.i] = (float)(1.0 / acc);
   }
 }
@@ -1262,7 +1262,7 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_priv(
 #pragma unroll
   for (int b = 0; b < 4; ++b) off += (uint32_t)__popcll(__ballot((keep >> b) & 1u) & below) << b;
   if (!tl.valid) return;
-  r_out[ii] = acc;
+  if (r_out) r_out[ii] = acc;
   q_out[ii] = (T)(1.0 / acc);
   const bool miss = cnt > (uint32_t)kCacheLane || off + keep > (uint32_t)kCacheWave;
   if (!miss) {
@@ -1322,7 +1322,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
     const T qi = q[ii];
     const uint32_t meta = nb_meta[ii];
     if ((meta & 15u) != kCacheMiss) {
-      racc = r_in[ii];
+      racc = sym ? 1.0 : r_in[ii];  // only the row normalisation divides by r_i
       const uint32_t c = meta & 15u;
       const int64_t e0 = wave_tile() * kCacheWave + (meta >> 4);
       // neighbours NB at a time, all their loads in flight together; at most
@@ -2172,7 +2172,7 @@ __global__ __launch_bounds__(kBlock) void k_half_rowsum_fin(PairArgs a) {
     r[0] = a.half_own[tl.i];
     half_gather<1>(a, P, tl.i, r);
   }
-  a.r_out[tl.i] = r[0];
+  if (a.r_out) a.r_out[tl.i] = r[0];
   ((float*)a.q_out)[tl.i] = (float)(1.0 / r[0]);
 }
 
@@ -2196,7 +2196,7 @@ __global__ __launch_bounds__(kBlock) void k_half_exchange_fin(PairArgs a) {
 #pragma unroll
     for (int v = 0; v < SMAX; ++v) acc[v] = a.half_own[(int64_t)ii * SMAX + v];
     half_gather<SMAX>(a, P, ii, acc);
-    racc = a.r_out[ii];
+    racc = a.norm == 0 ? 1.0 : a.r_out[ii];  // only the row normalisation divides by r_i
   }
   exchange_epilogue<float, SMAX, 64>(P, a.norm == 0, acc, racc, Mi, tl.valid, tl.i, (float*)a.mass_out, a.S,
                                      a.react_a, a.react_b, a.audit_part, wave_tile());
