@@ -901,7 +901,7 @@ rwpt_status rwpt_init_ensemble(rwpt_ctx* c, int32_t n_real, const int64_t* n_per
   c->dense = dense_ok && c->cfg.path != RWPT_PATH_SPARSE;
   c->cap = std::max<int64_t>(64, (N + 63) / 64 * 64);
   const size_t ts = c->tsize, cap = (size_t)c->cap;
-  const int PS = dim == 3 ? 4 : dim;  // position slots per particle (particle-major)
+  const int PS = dim;  // position slots per particle (particle-major, packed)
   HIPCHK(c, c->pos0.ensure(PS * cap * ts));
   HIPCHK(c, c->pos1.ensure(PS * cap * ts));
   const int Sa = padded_species(S);  // species slots per particle
@@ -1116,7 +1116,7 @@ rwpt_status rwpt_query_positions(rwpt_ctx* c, double* out) {
   c->err.clear();
   if (!c->initialized) return fail(c, RWPT_ESTATE, "query before rwpt_init_ensemble");
   if (!out && c->N > 0) return fail(c, RWPT_EINVAL, "out is NULL");
-  return fetch_sorted(c, c->pos0, c->dim, c->dim == 3 ? 4 : c->dim, out, false);
+  return fetch_sorted(c, c->pos0, c->dim, c->dim, out, false);
 }
 
 rwpt_status rwpt_audit(rwpt_ctx* c, double* out) {
@@ -1529,7 +1529,7 @@ rwpt_status rwpt_autotune(rwpt_ctx* c, double dt, double D, int32_t trial_steps)
   // snapshot of the state the tuning steps will overwrite
   const size_t ts = c->tsize, cap = (size_t)c->cap;
   const int Sa = padded_species(c->S);
-  const size_t npos = (c->dim == 3 ? 4 : c->dim) * cap * ts, nmass = Sa * cap * ts, naud = (size_t)c->n_real * (c->S + 1) * 8;
+  const size_t npos = c->dim * cap * ts, nmass = Sa * cap * ts, naud = (size_t)c->n_real * (c->S + 1) * 8;
   DevBuf sp, sm, si, sa, sc;
   rwpt_status result = RWPT_OK;
   const rwpt_config saved_cfg = c->cfg;
@@ -1692,7 +1692,7 @@ rwpt_status rwpt_transfer_noalloc(const rwpt_config* cfg, int32_t n, const void*
   const int64_t ncell = (int64_t)na.P.nc[0] * na.P.nc[1] * na.P.nc[2];
   const int32_t ntiles = (int32_t)((n + G - 1) / G);
   const int64_t cap = (int64_t)(n + 63) / 64 * 64;
-  const int PS = dim == 3 ? 4 : dim, Sa = padded_species(S);
+  const int PS = dim, Sa = padded_species(S);
   const int64_t nscan = (ncell + kScanChunk - 1) / kScanChunk + 1;
   // the pieces of the scratch area this call uses
   ScratchLayout L;

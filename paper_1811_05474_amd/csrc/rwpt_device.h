@@ -53,7 +53,7 @@ struct Tile {
 // Arguments of the pair kernels.  Floating-point arrays are binary32 or
 // binary64 according to the kernel instantiation.
 struct PairArgs {
-  const void* pos;         // [cap][PS] particle-major (PS = 1, 2, 4), cell-sorted
+  const void* pos;         // [cap][d] particle-major (packed), cell-sorted
   const void* mass_in;     // [cap][SP] particle-major (SP = 2, 4, 8 species slots)
   void* mass_out;          // [cap][SP]
   const void* q_in;        // 1 / r_i for the symmetric normalisation, [cap]

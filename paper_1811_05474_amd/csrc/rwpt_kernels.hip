@@ -4,8 +4,8 @@
 //   scatter, canonical in-cell order) -> row sums r_i -> weights + exchange +
 //   reaction + audit partials -> per-realisation audit.
 //
-// Layout: particle-major, positions pos[PS * p + k] (PS = 1, 2, 4 for 1-, 2-,
-// 3-D: one particle is one aligned vector load) and masses mass[SP * p + s]
+// Layout: particle-major, positions pos[d * p + k] (packed: one particle is
+// one vector load) and masses mass[SP * p + s]
 // (SP = 2, 4, 8 species slots, the unused ones zero), kept in cell-sorted order; id[p] maps a sorted slot back to the caller's
 // particle index.  Every reduction runs in a fixed order, so results are
 // bitwise reproducible run to run.

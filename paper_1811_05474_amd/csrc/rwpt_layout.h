@@ -1,11 +1,11 @@
 // rwpt_layout.h -- particle-major device layouts of the positions and masses
 // (internal to the HIP kernels).
 //
-// Positions: coordinate k of particle p at pos[PS * p + k], PS = 1, 2, 4 for
-// 1-, 2-, 3-D (the 3-D fourth slot is zero), so one particle is one aligned
-// vector load.  Masses: species s of particle p at mass[SP * p + s], SP = 2, 4
-// or 8 species slots (the unused slots hold zeros).  Gathers of a neighbour
-// are then one or two vector loads instead of one load per component.
+// Positions: coordinate k of particle p at pos[d * p + k] (packed, no padding:
+// a 3-D binary32 particle is one 12-byte load).  Masses: species s of
+// particle p at mass[SP * p + s], SP = 2, 4 or 8 species slots (the unused
+// slots hold zeros).  Gathers of a neighbour are then one or two vector loads
+// instead of one load per component.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -17,7 +17,13 @@ struct VecOf {
   typedef T type __attribute__((ext_vector_type(N)));
 };
 template <int DIM>
-constexpr int pos_stride() { return DIM == 3 ? 4 : DIM; }
+constexpr int pos_stride() { return DIM; }
+
+// Three packed coordinates (one vector load or store of 3 x sizeof(T) bytes).
+template <typename T>
+struct __attribute__((packed, aligned(sizeof(T)))) Packed3 {
+  T x, y, z;
+};
 
 template <typename T, int DIM>
 __device__ __forceinline__ void load_pos(const T* __restrict__ pos, int64_t j, T x[DIM]) {
@@ -28,7 +34,7 @@ __device__ __forceinline__ void load_pos(const T* __restrict__ pos, int64_t j, T
     x[0] = v.x;
     x[1] = v.y;
   } else {
-    const typename VecOf<T, 4>::type v = *(const typename VecOf<T, 4>::type*)(pos + 4 * j);
+    const Packed3<T> v = *(const Packed3<T>*)(pos + 3 * j);
     x[0] = v.x;
     x[1] = v.y;
     x[2] = v.z;
@@ -45,12 +51,11 @@ __device__ __forceinline__ void store_pos(T* __restrict__ pos, int64_t j, const 
     v.y = x[1];
     *(typename VecOf<T, 2>::type*)(pos + 2 * j) = v;
   } else {
-    typename VecOf<T, 4>::type v;
+    Packed3<T> v;
     v.x = x[0];
     v.y = x[1];
     v.z = x[2];
-    v.w = (T)0;
-    *(typename VecOf<T, 4>::type*)(pos + 4 * j) = v;
+    *(Packed3<T>*)(pos + 3 * j) = v;
   }
 }
 
