@@ -19,15 +19,32 @@ every pair of the realisation, and the roofline counts the pairs whose weight
 is at least 2^-40 (separation within sqrt(40 ln 2) sigma), the ones the kernel
 must evaluate to binary32 accuracy.
 
-Besides value, the line carries: roofline (the exchange kernel against the
-FP32 vector peak, or against HBM when its flops per algorithmic byte are
-below the machine balance; traffic from the committed rocprofv3 counter
-summary while the device sources match it), step_roofline (the whole step's
-algorithmic bytes against HBM), valu_probe (the row-broadcast pair kernels'
-evaluation rates against register-only kernels running the same
-per-candidate code, rwpt_probe_rate), host_io (one step fed from and returned
-to host memory, PCIe included), fp64 (the same run in binary64) and
-cpu_baseline (the CPU oracle on a bounded sample of the same workload).
+Besides value, the line carries:
+  roofline        the exchange kernel against the FP32 vector peak, or against
+                  HBM when its flops per algorithmic byte are below the machine
+                  balance; achieved from HIP events around the timed steps on
+                  the library's stream; traffic from the committed rocprofv3
+                  counter summary while the device sources match it (else null)
+  step_roofline   the whole step's algorithmic bytes against HBM
+  valu_probe      the row-broadcast pair kernels' evaluation rates against
+                  register-only kernels running the same per-candidate code
+                  (rwpt_probe_rate)
+  host_io         one step fed from and returned to host memory, PCIe included
+  err_vs_oracle_fp32, err_vs_oracle_fp64
+                  one step from the seeded state, sampled particles against the
+                  oracle, on identical positions and with the walk, each with
+                  its bar (--no-accuracy skips them)
+  fp64            the same run in binary64: its rate and phases, the FP32 path's
+                  speedup over it (fp32_speedup, stated only when both paths are
+                  within their bars; fp32_speedup_at says so), the two paths'
+                  normwise mass difference after the run and both audits' drift
+  config.tile_lanes, config.tiling_chosen_by
+                  the pair tiling timed and who chose it: the library default, a
+                  --tile-lanes flag, or rwpt_autotune (run outside the timed
+                  region for the 64-realisation batch; --no-autotune skips it)
+  cpu_baseline    the CPU oracle on a bounded sample of the same workload on
+                  the host's threads, with the CPU model, the thread count and a
+                  single-thread figure on a slab of the same workload
 """
 from __future__ import annotations
 
