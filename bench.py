@@ -22,8 +22,10 @@ must evaluate to binary32 accuracy.
 Besides value, the line carries:
   roofline        the exchange kernel against the FP32 vector peak, or against
                   HBM when its flops per algorithmic byte are below the machine
-                  balance; achieved from HIP events around the timed steps on
-                  the library's stream; traffic from the committed rocprofv3
+                  balance; the kernel's duration from HIP events around every
+                  kernel phase (on the library's stream) of an eager rerun of
+                  the same steps after the timed region; traffic from the
+                  committed rocprofv3
                   counter summary while the device sources match it (else null)
   step_roofline   the whole step's algorithmic bytes against HBM
   valu_probe      the row-broadcast pair kernels' evaluation rates against
