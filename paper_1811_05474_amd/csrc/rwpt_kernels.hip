@@ -374,6 +374,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter(int32_t n, const uint32_t* _
   tmp_key[dst] = k;
 }
 
+// The canonical gather takes kCanonItems particles per thread (block b covers
+// kCanonItems * kBlock consecutive sorted slots, item u at threadIdx.x +
+// u kBlock), with every item's loads issued before any of them is used, so
+// that the items' chains of dependent loads (slot -> cell start -> cell
+// members) overlap.  (Two items per thread in the scatter made it slower.)
+constexpr int kCanonItems = 2;
+
 // The atomic slot of the scatter depends on arrival order; ranking by the
 // (unique) particle id inside each cell makes the sorted order a function of
 // the positions alone: (cell, id).
@@ -386,24 +393,39 @@ __global__ __launch_bounds__(kBlock) void k_canon(
     const T* __restrict__ pos_in, T* __restrict__ pos_out, const T* __restrict__ mass_in,
     T* __restrict__ mass_out, uint32_t* __restrict__ id_out, uint32_t* __restrict__ skey,
     uint32_t* __restrict__ src_out) {
-  const int e = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (e >= n) return;
-  const uint32_t k = tmp_key[e];
-  const uint32_t src = tmp_src[e];
+  const int64_t e0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kCanonItems * kBlock) + threadIdx.x;
+  uint32_t k[kCanonItems], src[kCanonItems], my[kCanonItems], cs[kCanonItems], ce[kCanonItems];
+#pragma unroll
+  for (int u = 0; u < kCanonItems; ++u) {
+    const int64_t e = e0 + u * kBlock;
+    const int64_t q = e < n ? e : n - 1;  // a lane past the end repeats the last slot, stores nothing
+    k[u] = tmp_key[q];
+    src[u] = tmp_src[q];
+    my[u] = tmp_id[q];
+  }
   // issue the gathers first; the in-cell ranking below overlaps them
-  T x[DIM], m[SMAX];
-  load_pos<T, DIM>(pos_in, src, x);
-  if constexpr (MOVE) load_mass<T, SMAX>(mass_in, src, m);  // unused species slots are zero and stay zero
-  const uint32_t cs = cell_start[k], ce = cell_start[k + 1];
-  const uint32_t my = tmp_id[e];
-  uint32_t rank = 0;
-  for (uint32_t f = cs; f < ce; ++f) rank += (tmp_id[f] < my) ? 1u : 0u;
-  const uint32_t dst = cs + rank;
-  store_pos<T, DIM>(pos_out, dst, x);
-  if constexpr (MOVE) store_mass<T, SMAX>(mass_out, dst, m);
-  else src_out[dst] = src;
-  id_out[dst] = my;
-  skey[dst] = k;
+  T x[kCanonItems][DIM], m[kCanonItems][SMAX];
+#pragma unroll
+  for (int u = 0; u < kCanonItems; ++u) {
+    load_pos<T, DIM>(pos_in, src[u], x[u]);
+    if constexpr (MOVE) load_mass<T, SMAX>(mass_in, src[u], m[u]);  // unused species slots are zero and stay zero
+    cs[u] = cell_start[k[u]];
+    ce[u] = cell_start[k[u] + 1];
+  }
+#pragma unroll
+  for (int u = 0; u < kCanonItems; ++u) {
+    uint32_t rank = 0;
+    for (uint32_t f = cs[u]; f < ce[u]; ++f) rank += (tmp_id[f] < my[u]) ? 1u : 0u;
+    const int64_t e = e0 + u * kBlock;
+    if (e < n) {
+      const uint32_t dst = cs[u] + rank;
+      store_pos<T, DIM>(pos_out, dst, x[u]);
+      if constexpr (MOVE) store_mass<T, SMAX>(mass_out, dst, m[u]);
+      else src_out[dst] = src[u];
+      id_out[dst] = my[u];
+      skey[dst] = k[u];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1057,7 +1079,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
           }
 #pragma unroll
           for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
-          racc += (double)rr;
+          if (!sym) racc += (double)rr;  // r_i: only the row normalisation divides by it
         });
   }
   if constexpr (SPLIT > 1) {
@@ -1082,7 +1104,7 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
   for (int off = 16; off < 64; off <<= 1) {
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) acc[s] += __shfl_xor(acc[s], off);
-    racc += __shfl_xor(racc, off);
+    if (!sym) racc += __shfl_xor(racc, off);
   }
   exchange_epilogue<float, SMAX, G>(P, sym, acc, racc, Mi, tl.gl == 0 && tl.valid, tl.i, mout, S,
                                     react_a, react_b, audit_part, wave_tile<SPLIT>());
@@ -2273,6 +2295,9 @@ __global__ __launch_bounds__(kBlock) void k_na_store(int32_t n, int32_t S, const
 // ---------------------------------------------------------------------------
 
 static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+static inline unsigned canon_blocks_for(int64_t n) {
+  return (unsigned)((n + kCanonItems * kBlock - 1) / (kCanonItems * kBlock));
+}
 
 hipError_t launch_walk_key(int fp64, int dim, const void* pos_in, void* pos_out,
                            const uint32_t* id, int32_t n, const RealParams* rp,
@@ -2328,7 +2353,7 @@ hipError_t launch_canon(int fp64, int dim, int32_t n, const uint32_t* tmp_src,
                         const void* mass_in, void* mass_out, int32_t S,
                         uint32_t* id_out, uint32_t* skey, uint32_t* src_out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const dim3 g(blocks_for(n)), b(kBlock);
+  const dim3 g(canon_blocks_for(n)), b(kBlock);
 #define RWPT_CN(T, D)                                                                           \
   do {                                                                                          \
     if (S <= 2) RWPT_CN1(T, D, 2);                                                              \
