@@ -536,8 +536,9 @@ def main():
             "norm": "sym", "reaction": "A+B->0" if w.react else "none",
             "path": "dense" if dense else "sparse",
             "tile_lanes": r32["tiling"][0], "cell_refine": r32["tiling"][1],
-            "tiling_chosen_by": "rwpt_autotune (%.1f s, outside the timed region)" % r32["autotune_s"]
-            if r32["autotune_s"] is not None else "default",
+            "tiling_chosen_by": ("rwpt_autotune (%.1f s, outside the timed region)" % r32["autotune_s"]
+                                 if r32["autotune_s"] is not None
+                                 else ("--tile-lanes %d" % args.tile_lanes if args.tile_lanes else "default")),
             "unordered_pairs_per_step": unordered,
             "candidate_evaluations_per_step": r32["evaluations_per_step"],
         },
