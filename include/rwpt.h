@@ -169,7 +169,11 @@ rwpt_status rwpt_steps_taken(rwpt_ctx *ctx, int64_t *out);
 /* Count, for the current positions and the cutoff of (dt, D), the ordered
  * neighbour pairs j != i within the cutoff (pairs_out, summed over
  * realisations) and the candidate evaluations the sparse kernels perform
- * (evals_out, may be NULL).  Synchronous; does not change the state. */
+ * (evals_out, may be NULL).  With the half-stencil tiling (tile_lanes = -2)
+ * both counts come from the one-lane tiles of 64 particles (the same pairs;
+ * evals_out is then that enumeration's count, not the half stencil's own,
+ * which evaluates each unordered pair once).  Synchronous; does not change
+ * the state. */
 rwpt_status rwpt_count_pairs(rwpt_ctx *ctx, double dt, double D, int64_t *pairs_out,
                              int64_t *evals_out);
 
