@@ -589,31 +589,23 @@ __device__ __forceinline__ void exchange_epilogue(const RealParams& P, bool sym,
       if (P.active) dm = sym ? 0.25 * acc[s] : 0.5 * acc[s] / racc;
       Mn[s] = (double)Mi[s] + dm;
     }
+    // the reacting pair by its slot indices (uniform, < S <= SMAX: indexed
+    // register moves, not a select over every slot)
     if (react_a >= 0) {
-#pragma unroll
-      for (int s = 0; s < SMAX; ++s)
-        if (s == react_a) {
-#pragma unroll
-          for (int t2 = 0; t2 < SMAX; ++t2)
-            if (t2 == react_b) {
-              double m = Mn[s] < Mn[t2] ? Mn[s] : Mn[t2];
-              m = m > 0.0 ? m : 0.0;
-              Mn[s] -= m;
-              Mn[t2] -= m;
-            }
-        }
+      const double A = Mn[react_a], B = Mn[react_b];
+      double m = A < B ? A : B;
+      m = m > 0.0 ? m : 0.0;
+      Mn[react_a] = A - m;
+      Mn[react_b] = B - m;
     }
-    double va = 0.0, vb = 0.0;
     T out[SMAX];
 #pragma unroll
     for (int s = 0; s < SMAX; ++s) {
       out[s] = s < S ? (T)Mn[s] : (T)0;  // unused species slots stay zero
       tot[s] = (double)out[s];
-      if (s == react_a) va = tot[s];
-      if (s == react_b) vb = tot[s];
     }
     store_mass<T, SMAX>(mout, i, out);
-    tot[SMAX] = va - vb;
+    tot[SMAX] = react_a >= 0 ? tot[react_a] - tot[react_b] : 0.0;
   }
   // totals over lanes 0..G-1 (the other lanes hold zeros and are reduced
   // among themselves); value SMAX is sum(A - B)
