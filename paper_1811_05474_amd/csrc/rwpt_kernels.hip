@@ -1938,7 +1938,9 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
                     __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (w >= a.half_nitems) return;
   const int r = __builtin_amdgcn_readfirstlane(half_real(a.half_item_start, a.n_real, w));
-  const RealParams& P = a.rp[r];
+  // a local copy: the slot stores below could alias the parameter array for
+  // the compiler, which would then reload its fields after every store
+  const RealParams P = a.rp[r];
   if (!P.active || P.nseg <= 0) return;
   const float* __restrict__ pos = (const float*)a.pos;
   const float* __restrict__ min_ = (const float*)a.mass_in;
