@@ -1841,6 +1841,7 @@ __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : 
 // forward stencil rows in stencil order (directions 1, 2, ... counted whether
 // or not the target row exists, as the finalizers count them).
 struct HalfCursor {
+  uint32_t own_je;  // end of the own row's range (loaded with the tile)
   int f;            // next stencil entry (-1: the own row is next)
   int nfwd;         // forward stencil entries seen
   int dix;          // direction of the current range
@@ -1860,8 +1861,7 @@ __device__ __forceinline__ void half_advance(HalfCursor& c, const RealParams& P,
     if (c.f < 0) {
       c.f = 0;
       jb = t1;
-      const int xb = cxb + P.rx_own > nc0 - 1 ? nc0 - 1 : cxb + P.rx_own;
-      je = cell_start[rowbase + xb + 1];
+      je = c.own_je;
       dix = 0;
     } else {
       if (c.f >= P.n_stencil) return;
@@ -1982,32 +1982,59 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
 
   const uint32_t pb = cs[rowbase + c0], pe = cs[rowbase + c1 + 1];
   const float rc2 = P.rc2_f, esc = P.escale_f;
+  // a tile's particles, its cells along x and the end of its own-row range,
+  // loaded one tile ahead so that their latency overlaps the previous tile
+  struct TileIn {
+    float x[DIM], m[SMAX], q;
+    int cxa, cxb;
+    uint32_t own_je;
+  };
+  auto tile_load = [&](uint32_t t0) {
+    TileIn d;
+    const uint32_t t1 = t0 + 16 < pe ? t0 + 16 : pe;
+    const int32_t ii = gi < (int)(t1 - t0) ? (int32_t)t0 + gi : (int32_t)t1 - 1;
+    load_pos<float, DIM>(pos, ii, d.x);
+    d.q = 0.0f;
+#pragma unroll
+    for (int v = 0; v < SMAX; ++v) d.m[v] = 0.0f;
+    if constexpr (EXCH) {
+      d.q = q[ii];
+      load_mass<float, SMAX>(min_, ii, d.m);
+    }
+    d.cxa = (int)(a.skey[t0] - (uint32_t)rowbase);
+    d.cxb = (int)(a.skey[t1 - 1] - (uint32_t)rowbase);
+    const int xb = d.cxb + P.rx_own > nc0 - 1 ? nc0 - 1 : d.cxb + P.rx_own;
+    d.own_je = cs[rowbase + xb + 1];
+    return d;
+  };
+  TileIn tin;
+  if (pb < pe) tin = tile_load(pb);
   for (uint32_t t0 = pb; t0 < pe; t0 += 16) {
     const uint32_t t1 = t0 + 16 < pe ? t0 + 16 : pe;
     const int n_in = (int)(t1 - t0);
     const bool valid = gi < n_in;
     const int32_t ii = valid ? (int32_t)t0 + gi : (int32_t)t1 - 1;
+    const TileIn cur_tile = tin;
+    if (t1 < pe) tin = tile_load(t1);
     float xi[DIM];
-    load_pos<float, DIM>(pos, ii, xi);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) xi[k] = cur_tile.x[k];
     // a lane past the tile's end: its separations overflow to +inf, weight 0
     if (!valid) xi[0] = -3.0e38f;
-    float qi = 0.0f, Mi[SMAX];
+    const float qi = cur_tile.q;
+    float Mi[SMAX];
 #pragma unroll
-    for (int v = 0; v < SMAX; ++v) Mi[v] = 0.0f;
-    if constexpr (EXCH) {
-      qi = q[ii];
-      load_mass<float, SMAX>(min_, ii, Mi);
-    }
-    const int cxa = (int)(a.skey[t0] - (uint32_t)rowbase);
-    const int cxb = (int)(a.skey[t1 - 1] - (uint32_t)rowbase);
+    for (int v = 0; v < SMAX; ++v) Mi[v] = cur_tile.m[v];
+    const int cxa = cur_tile.cxa, cxb = cur_tile.cxb;
     double acc[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[v] = 0.0;
 
     // pairs inside the tile, from both ends: row g takes the rotations
     // 4g .. 4g + 3 of the tile's particles (all 16 over the four rows; the
-    // rotation 0 is the particle itself, weight 1)
-    {
+    // rotation 0 is the particle itself, weight 1).  Evaluated once the first
+    // chunk's loads are in flight, and added first.
+    auto self_tile = [&]() {
       float part[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) part[v] = 0.0f;
@@ -2032,7 +2059,7 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
       }
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[v] += (double)part[v];
-    }
+    };
 
     // forward candidates, 64 per chunk, the next chunk's loads issued before
     // the current chunk is computed
@@ -2110,6 +2137,7 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
       }
     };
     HalfCursor c;
+    c.own_je = cur_tile.own_je;
     c.f = -1;
     c.nfwd = 0;
     c.p = 0;
@@ -2121,6 +2149,7 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
       int dix;
       half_pick(c, P, a.st, cs, y, z, rowbase, cxa, cxb, t1, vbase, (int32_t)t0, j, has, dix);
       Cand cur = load(j, has, dix);
+      self_tile();
       while (true) {
         const bool next = c.valid;
         Cand nxt = cur;
@@ -2133,6 +2162,8 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
         if (!next) break;
         cur = nxt;
       }
+    } else {
+      self_tile();
     }
     // the particle's own sums over the four rows
 #pragma unroll
