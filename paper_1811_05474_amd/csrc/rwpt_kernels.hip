@@ -1840,47 +1840,67 @@ __device__ __forceinline__ int floordiv(int a, int b) { return a >= 0 ? a / b : 
 // row first (direction 0: particles after the tile up to the reach), then the
 // forward stencil rows in stencil order (directions 1, 2, ... counted whether
 // or not the target row exists, as the finalizers count them).
+// Forward rows whose candidate ranges a tile loads ahead, with its particles
+// (the others are looked up when the cursor reaches them).
+constexpr int kHalfPreRows = 2;
+
 struct HalfCursor {
-  uint32_t own_je;  // end of the own row's range (loaded with the tile)
-  int f;            // next stencil entry (-1: the own row is next)
-  int nfwd;         // forward stencil entries seen
+  uint32_t own_je;                                  // end of the own row's range
+  uint32_t fjb[kHalfPreRows], fje[kHalfPreRows];    // the first forward rows' ranges
+  int k;            // next forward row (-1: the own row is next)
+  int f;            // stencil entry to scan from for forward rows past the first kHalfPreRows
   int dix;          // direction of the current range
   uint32_t jb, je;  // current range of sorted indices
   uint32_t p;       // virtual index of jb
   bool valid;
 };
 
+// Moves the cursor to the next non-empty range: the own row's later
+// particles, then the forward rows in stencil order (direction 1 + their
+// index among the forward rows, counted whether or not the row exists); the
+// first NPRE forward rows come from the ranges loaded with the tile.
+template <int NPRE>
 __device__ __forceinline__ void half_advance(HalfCursor& c, const RealParams& P, const StencilRow* __restrict__ st,
                                              const uint32_t* __restrict__ cell_start, int y, int z, int64_t rowbase,
                                              int cxa, int cxb, uint32_t t1) {
   const int nc0 = P.nc[0], nc1 = P.nc[1], nc2 = P.nc[2];
   c.valid = false;
-  while (true) {
-    uint32_t jb, je;
-    int dix;
-    if (c.f < 0) {
-      c.f = 0;
-      jb = t1;
-      je = c.own_je;
-      dix = 0;
+  if (c.k < 0) {
+    c.k = 0;
+    if (c.own_je > t1) {
+      c.jb = t1;
+      c.je = c.own_je;
+      c.dix = 0;
+      c.valid = true;
+      return;
+    }
+  }
+  while (c.k < P.n_fwd) {
+    const int k = c.k++;
+    uint32_t jb = 0u, je = 0u;
+    if (k < NPRE) {
+#pragma unroll
+      for (int u = 0; u < NPRE; ++u)
+        if (u == k) {
+          jb = c.fjb[u];
+          je = c.fje[u];
+        }
     } else {
-      if (c.f >= P.n_stencil) return;
-      const StencilRow sr = st[P.stencil_off + c.f];
-      ++c.f;
-      if (!forward_row(sr)) continue;
-      dix = ++c.nfwd;
+      StencilRow sr = st[P.stencil_off + c.f++];
+      while (!forward_row(sr)) sr = st[P.stencil_off + c.f++];  // a k-th forward row exists: k < n_fwd
       const int ty = y + sr.dy, tz = z + sr.dz;
-      if (ty < 0 || ty >= nc1 || tz < 0 || tz >= nc2) continue;
-      const int64_t cb = P.cell_off + ((int64_t)tz * nc1 + ty) * nc0;
-      const int xa = cxa - sr.rx < 0 ? 0 : cxa - sr.rx;
-      const int xb = cxb + sr.rx > nc0 - 1 ? nc0 - 1 : cxb + sr.rx;
-      jb = cell_start[cb + xa];
-      je = cell_start[cb + xb + 1];
+      if (ty >= 0 && ty < nc1 && tz >= 0 && tz < nc2) {
+        const int64_t cb = P.cell_off + ((int64_t)tz * nc1 + ty) * nc0;
+        const int xa = cxa - sr.rx < 0 ? 0 : cxa - sr.rx;
+        const int xb = cxb + sr.rx > nc0 - 1 ? nc0 - 1 : cxb + sr.rx;
+        jb = cell_start[cb + xa];
+        je = cell_start[cb + xb + 1];
+      }
     }
     if (je > jb) {
       c.jb = jb;
       c.je = je;
-      c.dix = dix;
+      c.dix = k + 1;
       c.valid = true;
       return;
     }
@@ -1890,6 +1910,7 @@ __device__ __forceinline__ void half_advance(HalfCursor& c, const RealParams& P,
 // Lane's candidate of the chunk at virtual index vbase (jdummy, has = false
 // past the last range) and its direction; advances over ranges ending in the
 // chunk.
+template <int NPRE>
 __device__ __forceinline__ void half_pick(HalfCursor& c, const RealParams& P, const StencilRow* __restrict__ st,
                                           const uint32_t* __restrict__ cell_start, int y, int z, int64_t rowbase,
                                           int cxa, int cxb, uint32_t t1, uint32_t vbase, int32_t jdummy, int32_t& j,
@@ -1907,7 +1928,7 @@ __device__ __forceinline__ void half_pick(HalfCursor& c, const RealParams& P, co
     }
     if (c.p + len <= vbase + 64) {
       c.p += len;
-      half_advance(c, P, st, cell_start, y, z, rowbase, cxa, cxb, t1);
+      half_advance<NPRE>(c, P, st, cell_start, y, z, rowbase, cxa, cxb, t1);
     } else {
       break;
     }
@@ -1980,6 +2001,31 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
     }
   }
 
+  // the first NPRE forward rows (target row's first cell relative to the
+  // realisation's, reach; cb < 0: outside the grid) and the stencil entry
+  // after them.  The row-sum pass loads their ranges with each tile; the
+  // exchange pass, short of registers, looks them up as it goes.
+  constexpr int NPRE = EXCH ? 0 : kHalfPreRows;
+  int32_t pre_cb[kHalfPreRows];
+  int pre_rx[kHalfPreRows];
+  int f_pre = 0;
+  {
+    int nf = 0;
+    for (int f = 0; f < P.n_stencil && nf < NPRE; ++f) {
+      const StencilRow sr = a.st[P.stencil_off + f];
+      if (!forward_row(sr)) continue;
+      const int ty = y + sr.dy, tz = z + sr.dz;
+      const bool in = ty >= 0 && ty < nc1 && tz >= 0 && tz < nc2;
+#pragma unroll
+      for (int u = 0; u < NPRE; ++u)
+        if (u == nf) {
+          pre_cb[u] = in ? (tz * nc1 + ty) * nc0 : -1;
+          pre_rx[u] = sr.rx;
+        }
+      ++nf;
+      f_pre = f + 1;
+    }
+  }
   const uint32_t pb = cs[rowbase + c0], pe = cs[rowbase + c1 + 1];
   const float rc2 = P.rc2_f, esc = P.escale_f;
   // a tile's particles, its cells along x and the end of its own-row range,
@@ -1987,7 +2033,7 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
   struct TileIn {
     float x[DIM], m[SMAX], q;
     int cxa, cxb;
-    uint32_t own_je;
+    uint32_t own_je, fjb[kHalfPreRows], fje[kHalfPreRows];
   };
   auto tile_load = [&](uint32_t t0) {
     TileIn d;
@@ -2005,6 +2051,17 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
     d.cxb = (int)(a.skey[t1 - 1] - (uint32_t)rowbase);
     const int xb = d.cxb + P.rx_own > nc0 - 1 ? nc0 - 1 : d.cxb + P.rx_own;
     d.own_je = cs[rowbase + xb + 1];
+#pragma unroll
+    for (int u = 0; u < NPRE; ++u) {
+      d.fjb[u] = 0u;
+      d.fje[u] = 0u;
+      if (u < P.n_fwd && pre_cb[u] >= 0) {
+        const int fa = d.cxa - pre_rx[u] < 0 ? 0 : d.cxa - pre_rx[u];
+        const int fb = d.cxb + pre_rx[u] > nc0 - 1 ? nc0 - 1 : d.cxb + pre_rx[u];
+        d.fjb[u] = cs[P.cell_off + pre_cb[u] + fa];
+        d.fje[u] = cs[P.cell_off + pre_cb[u] + fb + 1];
+      }
+    }
     return d;
   };
   TileIn tin;
@@ -2138,16 +2195,21 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
     };
     HalfCursor c;
     c.own_je = cur_tile.own_je;
-    c.f = -1;
-    c.nfwd = 0;
+#pragma unroll
+    for (int u = 0; u < NPRE; ++u) {
+      c.fjb[u] = cur_tile.fjb[u];
+      c.fje[u] = cur_tile.fje[u];
+    }
+    c.k = -1;
+    c.f = f_pre;
     c.p = 0;
-    half_advance(c, P, a.st, cs, y, z, rowbase, cxa, cxb, t1);
+    half_advance<NPRE>(c, P, a.st, cs, y, z, rowbase, cxa, cxb, t1);
     if (c.valid) {
       uint32_t vbase = 0;
       int32_t j;
       bool has;
       int dix;
-      half_pick(c, P, a.st, cs, y, z, rowbase, cxa, cxb, t1, vbase, (int32_t)t0, j, has, dix);
+      half_pick<NPRE>(c, P, a.st, cs, y, z, rowbase, cxa, cxb, t1, vbase, (int32_t)t0, j, has, dix);
       Cand cur = load(j, has, dix);
       self_tile();
       while (true) {
@@ -2155,7 +2217,7 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
         Cand nxt = cur;
         if (next) {
           vbase += 64;
-          half_pick(c, P, a.st, cs, y, z, rowbase, cxa, cxb, t1, vbase, (int32_t)t0, j, has, dix);
+          half_pick<NPRE>(c, P, a.st, cs, y, z, rowbase, cxa, cxb, t1, vbase, (int32_t)t0, j, has, dix);
           nxt = load(j, has, dix);
         }
         compute(cur);
