@@ -2003,9 +2003,10 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
 
   // the first NPRE forward rows (target row's first cell relative to the
   // realisation's, reach; cb < 0: outside the grid) and the stencil entry
-  // after them.  The row-sum pass loads their ranges with each tile; the
-  // exchange pass, short of registers, looks them up as it goes.
-  constexpr int NPRE = EXCH ? 0 : kHalfPreRows;
+  // after them, whose ranges are loaded with each tile (the exchange pass,
+  // short of registers, takes one row ahead and looks the others up as it
+  // goes).
+  constexpr int NPRE = EXCH ? 1 : kHalfPreRows;
   int32_t pre_cb[kHalfPreRows];
   int pre_rx[kHalfPreRows];
   int f_pre = 0;
