@@ -44,6 +44,21 @@ __device__ __forceinline__ int64_t wave_tile() {
   return SPLIT > 1 ? blk : blk * (kBlock / 64) + wave;
 }
 
+// Maximum of v over the 64 lanes of the wave (all active); wave-uniform.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int m = 32; m; m >>= 1) {
+    const uint32_t t = __shfl_xor(v, m);
+    v = t > v ? t : v;
+  }
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Between a wave's LDS stores and its loads of what other lanes of the same
+// wave stored: the LDS executes one wave's operations in order, so only the
+// compiler has to be kept from moving the loads above the stores.
+__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): 10 rounds of the
 // multiply/xor S-box with the key bumped by the golden-ratio and sqrt(3)-1
 // Weyl constants between rounds.
@@ -1229,8 +1244,9 @@ __device__ __forceinline__ void priv_walk(const RealParams& P, const uint32_t* _
   }
 }
 
+// (eight waves per SIMD: the binary32 form then fits 64 VGPRs without spills)
 template <typename T, int DIM, bool IND>
-__global__ __launch_bounds__(kBlock) void k_rowsum_priv(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_rowsum_priv(
     const T* __restrict__ pos, const uint32_t* __restrict__ cell_start, const Tile* __restrict__ tiles,
     const int32_t ntiles, const RealParams* __restrict__ rp, double* __restrict__ r_out,
     T* __restrict__ q_out, uint16_t* __restrict__ nb_meta, uint32_t* __restrict__ nb_idx,
@@ -1281,40 +1297,49 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_priv(
   uint32_t off = 0;
 #pragma unroll
   for (int b = 0; b < 4; ++b) off += (uint32_t)__popcll(__ballot((keep >> b) & 1u) & below) << b;
+  // Lanes whose entries would pass the end of the wave's region come after
+  // every lane that keeps its entries (the offsets only grow), so the kept
+  // entries are [0, nent) of the region.
+  const bool miss = cnt > (uint32_t)kCacheLane || off + keep > (uint32_t)kCacheWave;
+  const uint32_t nent = wave_max_u32(miss ? 0u : off + keep);
+  // The wave writes its entries flat, entry e by lane e mod 64: coalesced
+  // stores and one gather of the previous slots per 64 entries, instead of
+  // each lane storing its own up to kCacheLane entries.  The entry's owner
+  // is the last lane whose offset is <= e (a lane with no entries shares its
+  // offset with the next lane).
+  wave_lds_fence();
+  const int64_t wbase = wave_tile() * kCacheWave;
+  for (uint32_t r0 = 0; r0 < nent; r0 += 64) {
+    const uint32_t e = r0 + (uint32_t)lane;
+    int o = 0;
+#pragma unroll
+    for (int b = 32; b; b >>= 1) o = __shfl(off, o + b) <= e ? o + b : o;
+    // every lane takes part in the permutes (one from a disabled lane reads zero)
+    const uint32_t off_o = __shfl(off, o);
+    const bool have = e < nent;
+    const uint32_t k = have ? e - off_o : 0u;
+    const uint32_t j = sh_j[threadIdx.x >> 6][k * 64 + (have ? o : lane)];
+    const T w = sh_w[threadIdx.x >> 6][k * 64 + (have ? o : lane)];
+    uint32_t s = 0;
+    if constexpr (IND) s = src_of[have ? j : 0u];
+    if (have) {
+      nb_idx[wbase + e] = j;
+      nb_w[wbase + e] = w;
+      if constexpr (IND) nb_src[wbase + e] = s;
+    }
+  }
   if (!tl.valid) return;
   if (r_out) r_out[ii] = acc;
   q_out[ii] = (T)(1.0 / acc);
-  const bool miss = cnt > (uint32_t)kCacheLane || off + keep > (uint32_t)kCacheWave;
-  if (!miss) {
-    // all reads first (LDS, then the previous slots), then the stores, so the
-    // lane waits for one round trip
-    const int64_t e0 = wave_tile() * kCacheWave + off;
-    uint32_t cj[kCacheLane], cs[kCacheLane];
-    T cw[kCacheLane];
-#pragma unroll
-    for (int k = 0; k < kCacheLane; ++k) {
-      cj[k] = (uint32_t)k < keep ? lj[k * 64] : 0u;
-      cw[k] = (uint32_t)k < keep ? lw[k * 64] : (T)0;
-    }
-    if constexpr (IND) {
-#pragma unroll
-      for (int k = 0; k < kCacheLane; ++k) cs[k] = (uint32_t)k < keep ? src_of[cj[k]] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < kCacheLane; ++k)
-      if ((uint32_t)k < keep) {
-        nb_idx[e0 + k] = cj[k];
-        nb_w[e0 + k] = cw[k];
-        if constexpr (IND) nb_src[e0 + k] = cs[k];
-      }
-  }
   nb_meta[ii] = miss ? (uint16_t)kCacheMiss : (uint16_t)(keep ? ((off << 4) | keep) : 0u);
 }
 
-// Exchange with the row-sum pass's neighbour cache: a cached lane reads its
-// neighbours' indices and weights (no positions, no search); a lane marked as
-// a miss walks its stencil rows as the row-sum pass did.  r_i for the row
-// normalisation comes from the row-sum pass.
+// Exchange with the row-sum pass's neighbour cache.  The wave reads its
+// cached entries flat, entry e by lane e mod 64 (coalesced loads, one gather
+// of the neighbours' q and masses per 64 entries), stages them in LDS, and
+// each lane then adds its own entries in their order: no positions, no
+// search.  A lane marked as a miss walks its stencil rows as the row-sum pass
+// did.  r_i for the row normalisation comes from the row-sum pass.
 template <typename T, int DIM, int SMAX, bool IND>
 __global__ __launch_bounds__(kBlock) void k_exchange_priv(
     const T* __restrict__ pos, const T* __restrict__ min_, T* __restrict__ mout,
@@ -1338,72 +1363,79 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
   for (int s = 0; s < SMAX; ++s) acc[s] = 0.0;
   double racc = 0.0;
   const bool sym = (norm == 0);
-  if (P.active && tl.valid) {
-    const T qi = q[ii];
-    const uint32_t meta = nb_meta[ii];
-    if ((meta & 15u) != kCacheMiss) {
-      racc = sym ? 1.0 : r_in[ii];  // only the row normalisation divides by r_i
-      const uint32_t c = meta & 15u;
-      const int64_t e0 = wave_tile() * kCacheWave + (meta >> 4);
-      // neighbours NB at a time, all their loads in flight together; at most
-      // kCacheLane terms, summed in the path's precision, then widened
-      constexpr int NB = SMAX * sizeof(T) <= 16 ? 4 : 2;
-      T accc[SMAX];
+  const bool mine = P.active && tl.valid;
+  const T qi = mine ? q[ii] : (T)0;
+  const uint32_t meta = mine ? (uint32_t)nb_meta[ii] : kCacheMiss;
+  const bool cached = mine && (meta & 15u) != kCacheMiss;
+  const uint32_t c = cached ? meta & 15u : 0u, off = meta >> 4;
+  // the kept entries of the wave are [0, nent) of its region
+  const uint32_t nent = wave_max_u32(cached ? off + c : 0u);
+  const uint32_t cmax = wave_max_u32(c);
+  // at most kCacheLane terms per lane, summed in the path's precision, then widened
+  T accc[SMAX];
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) accc[s] = (T)0;
-      for (uint32_t k0 = 0; k0 < c; k0 += NB) {
-        uint32_t jv[NB], sv[NB];
-        T wv[NB];
+  for (int s = 0; s < SMAX; ++s) accc[s] = (T)0;
+  __shared__ T st_m[kBlock / 64][64 * SMAX];  // staged masses of the round's entries
+  __shared__ T st_wq[kBlock / 64][64 * 2];    // staged (w_ij, q_j)
+  T* const sm = st_m[threadIdx.x >> 6];
+  T* const swq = st_wq[threadIdx.x >> 6];
+  const int lane = threadIdx.x & 63;
+  const int64_t wbase = wave_tile() * kCacheWave;
+  for (uint32_t r0 = 0; r0 < nent; r0 += 64) {
+    const uint32_t e = r0 + (uint32_t)lane;
+    const int64_t ge = wbase + (e < nent ? e : 0u);  // entry 0 exists when nent > 0
+    const uint32_t j = nb_idx[ge];
+    const uint32_t sj = IND ? nb_src[ge] : j;
+    typename VecOf<T, 2>::type wq;
+    wq.x = nb_w[ge];
+    wq.y = q[j];
+    T Mj[SMAX];
+    load_mass<T, SMAX>(min_, sj, Mj);
+    wave_lds_fence();  // the previous round's LDS loads stay before these stores
+    store_mass<T, SMAX>(sm, lane, Mj);
+    *(typename VecOf<T, 2>::type*)(swq + 2 * lane) = wq;
+    wave_lds_fence();
+    for (uint32_t k = 0; k < cmax; ++k) {
+      const uint32_t ek = off + k - r0;  // the entry's lane in this round
+      if (k < c && off + k >= r0 && ek < 64u) {
+        T mj[SMAX];
+        load_mass<T, SMAX>(sm, ek, mj);
+        const typename VecOf<T, 2>::type v = *(const typename VecOf<T, 2>::type*)(swq + 2 * ek);
+        const T p = sym ? v.x * (qi + v.y) : v.x;
 #pragma unroll
-        for (int u = 0; u < NB; ++u) {
-          const bool ok = k0 + u < c;
-          const int64_t e = e0 + (ok ? k0 + u : 0);
-          jv[u] = ok ? nb_idx[e] : (uint32_t)ii;
-          wv[u] = ok ? nb_w[e] : (T)0;
-          if constexpr (IND) sv[u] = ok ? nb_src[e] : src_of[ii];
-          else sv[u] = jv[u];
-        }
-        T qj[NB], Mj[NB][SMAX];
+        for (int s = 0; s < SMAX; ++s) accc[s] += p * (mj[s] - Mi[s]);
+      }
+    }
+  }
+  if (cached) {
+    racc = sym ? 1.0 : r_in[ii];  // only the row normalisation divides by r_i
 #pragma unroll
-        for (int u = 0; u < NB; ++u) {
-          qj[u] = q[jv[u]];
-          load_mass<T, SMAX>(min_, sv[u], Mj[u]);
-        }
+    for (int s = 0; s < SMAX; ++s) acc[s] = (double)accc[s];
+  } else if (mine) {
+    T xi[DIM];
+    load_pos<T, DIM>(pos, ii, xi);
+    const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
+    for_own_rows<T, DIM>(P, st, cell_start, skey[ii] - (uint32_t)P.cell_off, [&](uint32_t jb, uint32_t je) {
+      T accr[SMAX];
 #pragma unroll
-        for (int u = 0; u < NB; ++u) {
-          const T p = sym ? wv[u] * (qi + qj[u]) : wv[u];  // 0 past the lane's count
+      for (int s = 0; s < SMAX; ++s) accr[s] = (T)0;
+      T rr = (T)0;
+      for (uint32_t j = jb; j < je; ++j) {
+        const T s2 = sep2<T, DIM>(xi, pos, j);
+        if (!(s2 <= rc2)) continue;  // sparse: most candidates miss, skip their loads
+        const T w = wfn(s2, esc);
+        // species slots S..SMAX-1 exist and hold zeros
+        const T p = sym ? w * (qi + q[j]) : w;
+        rr += w;
+        T mj[SMAX];
+        load_mass<T, SMAX>(min_, IND ? src_of[j] : j, mj);
 #pragma unroll
-          for (int s = 0; s < SMAX; ++s) accc[s] += p * (Mj[u][s] - Mi[s]);
-        }
+        for (int s = 0; s < SMAX; ++s) accr[s] += p * (mj[s] - Mi[s]);
       }
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) acc[s] = (double)accc[s];
-    } else {
-      T xi[DIM];
-      load_pos<T, DIM>(pos, ii, xi);
-      const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
-      for_own_rows<T, DIM>(P, st, cell_start, skey[ii] - (uint32_t)P.cell_off, [&](uint32_t jb, uint32_t je) {
-        T accr[SMAX];
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s) accr[s] = (T)0;
-        T rr = (T)0;
-        for (uint32_t j = jb; j < je; ++j) {
-          const T s2 = sep2<T, DIM>(xi, pos, j);
-          if (!(s2 <= rc2)) continue;  // sparse: most candidates miss, skip their loads
-          const T w = wfn(s2, esc);
-          // species slots S..SMAX-1 exist and hold zeros
-          const T p = sym ? w * (qi + q[j]) : w;
-          rr += w;
-          T mj[SMAX];
-          load_mass<T, SMAX>(min_, IND ? src_of[j] : j, mj);
-#pragma unroll
-          for (int s = 0; s < SMAX; ++s) accr[s] += p * (mj[s] - Mi[s]);
-        }
-#pragma unroll
-        for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
-        racc += (double)rr;
-      });
-    }
+      for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
+      racc += (double)rr;
+    });
   }
   exchange_epilogue<T, SMAX, 64>(P, sym, acc, racc, Mi, tl.valid, tl.i, mout, S, react_a, react_b,
                                  audit_part, wave_tile());
