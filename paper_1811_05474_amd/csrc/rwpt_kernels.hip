@@ -1415,26 +1415,21 @@ __global__ __launch_bounds__(kBlock) void k_exchange_priv(
     T xi[DIM];
     load_pos<T, DIM>(pos, ii, xi);
     const T rc2 = rc2_of<T>(P), esc = escale_of<T>(P);
+    // each term is added in binary64 as it is found (the terms are few; no
+    // binary32 partials beside the binary64 sums)
     for_own_rows<T, DIM>(P, st, cell_start, skey[ii] - (uint32_t)P.cell_off, [&](uint32_t jb, uint32_t je) {
-      T accr[SMAX];
-#pragma unroll
-      for (int s = 0; s < SMAX; ++s) accr[s] = (T)0;
-      T rr = (T)0;
       for (uint32_t j = jb; j < je; ++j) {
         const T s2 = sep2<T, DIM>(xi, pos, j);
         if (!(s2 <= rc2)) continue;  // sparse: most candidates miss, skip their loads
         const T w = wfn(s2, esc);
         // species slots S..SMAX-1 exist and hold zeros
         const T p = sym ? w * (qi + q[j]) : w;
-        rr += w;
+        racc += (double)w;
         T mj[SMAX];
         load_mass<T, SMAX>(min_, IND ? src_of[j] : j, mj);
 #pragma unroll
-        for (int s = 0; s < SMAX; ++s) accr[s] += p * (mj[s] - Mi[s]);
+        for (int s = 0; s < SMAX; ++s) acc[s] += (double)(p * (mj[s] - Mi[s]));
       }
-#pragma unroll
-      for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
-      racc += (double)rr;
     });
   }
   exchange_epilogue<T, SMAX, 64>(P, sym, acc, racc, Mi, tl.valid, tl.i, mout, S, react_a, react_b,
