@@ -786,6 +786,34 @@ def test_private_lists_cached_and_missed_neighbours(dim, mean_nb, prec, norm):
     ens.close()
 
 
+@pytest.mark.parametrize("mean_nb", [2.5, 6.0])
+@pytest.mark.parametrize("prec,norm", [(F32, rwpt.RWPT_NORM_SYM), (F64, rwpt.RWPT_NORM_ROW)])
+def test_private_lists_eight_species_in_several_rounds(mean_nb, prec, norm):
+    # 3-D, eight species: a wave keeps 2.5 or 6 neighbours per lane on average,
+    # so its cached entries take three or four rounds of 64 lanes (6.0: many
+    # waves also fill their 256-entry region and send lanes to the stencil
+    # walk); every species of every staged entry must reach its own lane
+    n, dt, seed = 20000, 0.1, 7100
+    rc = (mean_nb / ((n - 1) * 4.0 * math.pi / 3.0)) ** (1.0 / 3.0)
+    D = rc * rc / (72.0 * dt)
+    x = W.positions(n, 3, seed)
+    M = W.masses(n, 8, seed)
+    if prec == F32:
+        x, M = f32(x), f32(M)
+    ens = make(dim=3, S=8, rw=1.0, prec=prec, norm=norm, seed=seed, lanes=-1)
+    ens.init([n], x, M)
+    onorm = oracle.NORM_SYM if norm == rwpt.RWPT_NORM_SYM else oracle.NORM_ROW
+    lo, hi = (0.0,) * 3, (1.0,) * 3
+    for step, (xr, mr) in enumerate(OS.steps(x, M, 2, D, dt, seed, lo, hi, prec == F32, norm=onorm)):
+        ens.step(dt, D, 1)
+        pos, got = ens.positions(), ens.masses()
+        assert np.abs(pos - xr).max() < (2e-6 if prec == F32 else 1e-12)
+        check_err(got, mr, walk_tol(prec, D, dt), step)
+    pairs, _ = ens.count_pairs(dt, D)
+    assert 0.5 * mean_nb * n < pairs < 1.5 * mean_nb * n
+    ens.close()
+
+
 # ---------------------------------------------- device input and state summary ----
 
 def test_init_from_device_buffers_matches_host_init():
