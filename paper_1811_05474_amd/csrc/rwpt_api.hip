@@ -83,7 +83,7 @@ struct rwpt_ctx {
   DevBuf d_rp, d_st, d_tiles, d_tile_start, d_real_start, d_blk_real;
   DevBuf audit_part, audit_out, step_ctr, counts, d_chunks, d_chunk_start, chunk_part, audit_done;
   DevBuf bbox, bparts;  // full-matrix path
-  DevBuf half_slots, half_own, d_item_start;  // half-stencil tiling
+  DevBuf half_slots, half_own, d_item_start, d_item_real;  // half-stencil tiling
   int64_t half_nitems = 0;
   bool dense = false;   // full-matrix path selected at init
   float dense_escale = 0.0f, dense_skip_s2 = 0.0f;
@@ -457,13 +457,32 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
   // half-stencil tiling: work items (row, segment) of every realisation, and
   // slot planes npar (1 + forward rows) deep
   std::vector<int64_t> item_start(c->n_real + 1, 0);
+  std::vector<int32_t> item_real(c->n_real, 0);
   int max_fwd = 0;
   c->half_nitems = 0;
   if (half) {
+    // dispatch order: realisations by decreasing estimated cost per work item
+    // (particles per item x candidates per particle), so that the longest
+    // items start first and the short ones fill the end of the launch
+    std::vector<double> cost(c->n_real, 0.0);
     for (int r = 0; r < c->n_real; ++r) {
-      RealParams& P = c->h_rp[r];
+      const RealParams& P = c->h_rp[r];
+      const int64_t items = (int64_t)P.nseg * P.nc[1] * P.nc[2];
+      const int64_t cells = (int64_t)P.nc[0] * P.nc[1] * P.nc[2];
+      if (items <= 0 || cells <= 0) continue;
+      int64_t stencil_cells = 0;
+      for (int f = 0; f < P.n_stencil; ++f) stencil_cells += 2 * c->h_st[P.stencil_off + f].rx + 1;
+      const double nr = (double)(c->real_start[r + 1] - c->real_start[r]);
+      cost[r] = (nr / (double)items) * (nr / (double)cells) * (double)stencil_cells;
+    }
+    std::vector<int32_t> ord(c->n_real);
+    for (int r = 0; r < c->n_real; ++r) ord[r] = r;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    for (int k = 0; k < c->n_real; ++k) {
+      RealParams& P = c->h_rp[ord[k]];
       P.item_off = c->half_nitems;
-      item_start[r] = c->half_nitems;
+      item_start[k] = c->half_nitems;
+      item_real[k] = ord[k];
       c->half_nitems += (int64_t)P.nseg * P.nc[1] * P.nc[2];
       max_fwd = std::max(max_fwd, P.n_fwd);
     }
@@ -495,6 +514,9 @@ static rwpt_status build_grid(rwpt_ctx* c, double dt, double D) {
     HIPCHK(c, c->half_own.ensure((size_t)c->cap * Sa * sizeof(double)));
     HIPCHK(c, c->d_item_start.ensure(item_start.size() * sizeof(int64_t)));
     HIPCHK(c, hipMemcpyAsync(c->d_item_start.p, item_start.data(), item_start.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, c->d_item_real.ensure(item_real.size() * sizeof(int32_t)));
+    HIPCHK(c, hipMemcpyAsync(c->d_item_real.p, item_real.data(), item_real.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, c->stream));
   }
   if (c->dense) {
@@ -569,6 +591,7 @@ static PairArgs pair_args(rwpt_ctx* c) {
   a.half_slots = c->half_slots.as<float>();
   a.half_own = c->half_own.as<double>();
   a.half_item_start = c->d_item_start.as<int64_t>();
+  a.half_item_real = c->d_item_real.as<int32_t>();
   a.half_nitems = c->half_nitems;
   a.half_cap = c->cap;
   a.n_real = c->n_real;
@@ -1800,7 +1823,8 @@ void rwpt_destroy(rwpt_ctx* c) {
                       &c->d_tile_start, &c->d_real_start, &c->d_blk_real, &c->audit_part, &c->audit_out,
                       &c->step_ctr, &c->counts, &c->d_chunks, &c->d_chunk_start, &c->chunk_part,
                       &c->audit_done, &c->bbox, &c->bparts, &c->nb_meta, &c->nb_idx, &c->nb_w,
-                      &c->nb_src, &c->src_of, &c->half_slots, &c->half_own, &c->d_item_start};
+                      &c->nb_src, &c->src_of, &c->half_slots, &c->half_own, &c->d_item_start,
+                      &c->d_item_real};
     for (DevBuf* b : bufs) b->release();
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   }

@@ -90,7 +90,12 @@ struct PairArgs {
   // half_own[cap][V]
   float* half_slots;
   double* half_own;
-  const int64_t* half_item_start;  // [n_real + 1] first work item of each realisation
+  // work items in dispatch order: the realisations by decreasing cost per
+  // item, each realisation's items in (row, segment) order; position k of
+  // that order holds realisation half_item_real[k] and starts at item
+  // half_item_start[k]
+  const int64_t* half_item_start;  // [n_real + 1]
+  const int32_t* half_item_real;   // [n_real]
   int64_t half_nitems;
   int64_t half_cap;                // particles per slot plane
   int32_t n_real;

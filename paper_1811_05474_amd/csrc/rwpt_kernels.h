@@ -80,6 +80,8 @@ constexpr int kHalfParities = 2;
 // Candidate evaluations per work item of the half-stencil tiling aimed at on
 // average (segments are widened up to this where neighbourhoods are sparse).
 constexpr int64_t kHalfTarget = 32768;
+// Consecutive blocks of the half-stencil launch that one XCD takes in turn.
+constexpr int64_t kHalfGroup = 16;
 hipError_t launch_rowsum(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 hipError_t launch_exchange(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);
 hipError_t launch_count(int fp64, int dim, int log2l, const PairArgs& a, hipStream_t s);

@@ -1962,7 +1962,8 @@ __device__ __forceinline__ void half_pick(HalfCursor& c, const RealParams& P, co
   }
 }
 
-// Realisation of work item w (binary search over the first items).
+// Dispatch position (a realisation, in the order of item_start) of work item
+// w: binary search over the first items.
 __device__ __forceinline__ int half_real(const int64_t* __restrict__ item_start, int n_real, int64_t w) {
   int lo = 0, hi = n_real - 1;
   while (lo < hi) {
@@ -1982,10 +1983,24 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
   constexpr int V = EXCH ? SMAX : 1;
   const int lane = threadIdx.x & 63;
   const int gi = lane & 15, gl = lane >> 4;
-  const int64_t w = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) +
-                    __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // Items are numbered in dispatch order (realisations by decreasing cost per
+  // item).  Blocks are handed to the eight XCDs in turn, so in every round of
+  // 8 kHalfGroup launch-order blocks the XCDs each take kHalfGroup
+  // consecutive blocks (4 kHalfGroup neighbouring items, which share their
+  // halo rows in that XCD's L2): every XCD gets a like share of the costly
+  // items and runs its items from the longest.  The last, partial round keeps
+  // the launch order.
+  const int64_t b = blockIdx.x;
+  constexpr int64_t kRound = 8 * kHalfGroup;
+  int64_t lb = b;
+  if (b < ((int64_t)gridDim.x / kRound) * kRound) {
+    const int64_t rr = b % kRound;
+    lb = (b - rr) + (rr % 8) * kHalfGroup + rr / 8;
+  }
+  const int64_t w = lb * (kBlock / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (w >= a.half_nitems) return;
-  const int r = __builtin_amdgcn_readfirstlane(half_real(a.half_item_start, a.n_real, w));
+  const int k = __builtin_amdgcn_readfirstlane(half_real(a.half_item_start, a.n_real, w));
+  const int r = a.half_item_real[k];
   // a local copy: the slot stores below could alias the parameter array for
   // the compiler, which would then reload its fields after every store
   const RealParams P = a.rp[r];
@@ -1997,7 +2012,7 @@ __global__ __launch_bounds__(kBlock) void k_half_pairs(PairArgs a) {
   const int64_t cap = a.half_cap;
   const int nc0 = P.nc[0], nc1 = P.nc[1], nc2 = P.nc[2];
   const int W = P.seg_w;
-  const int64_t li = w - a.half_item_start[r];
+  const int64_t li = w - a.half_item_start[k];
   const int row = (int)(li / P.nseg), sg = (int)(li % P.nseg);
   const int y = row % nc1, z = row / nc1;
   const int64_t rowbase = P.cell_off + (int64_t)row * nc0;
