@@ -30,8 +30,13 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kColTile = 32;   // columns (j) per MFMA K-step and per bounding box
-constexpr int kRowTile = 16;   // rows (i) per wave in the exchange pass
-constexpr int kRowTileSum = 64;  // rows per wave in the row-sum pass
+constexpr int kRowTile = 16;   // rows (i) per block in the exchange pass
+constexpr int kRowTileSum = 64;  // rows per block in the row-sum pass
+// Waves that share one row tile, each taking every kSumWaves-th (kExWaves-th)
+// near column tile, so that a 32768-particle matrix gives 8 waves per SIMD
+// instead of one or two; their partial sums are added in wave order.
+constexpr int kSumWaves = 16;  // row-sum pass: one block of 1024 threads per 64-row tile
+constexpr int kExWaves = 4;    // exchange pass: one block of 256 threads per 16-row tile
 
 __device__ __forceinline__ float bf16_to_f32(__bf16 v) { return (float)v; }
 
@@ -118,17 +123,18 @@ __device__ __forceinline__ void load_box(const float* __restrict__ bbox, int t, 
   for (int k = 0; k < 2 * DIM; ++k) out[k] = bbox[(int64_t)t * 2 * DIM + k];
 }
 
-// Pass 1: one lane per row, column tiles broadcast through scalar loads.
+// Pass 1: one lane per row, column tiles broadcast through scalar loads; the
+// kSumWaves waves of a block share the block's 64 rows, wave w taking the
+// near column tiles t = w mod kSumWaves.
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_dense_rowsum(const float* __restrict__ pos, const int32_t n, const float* __restrict__ bbox,
+__global__ __launch_bounds__(64 * kSumWaves) void k_dense_rowsum(const float* __restrict__ pos, const int32_t n, const float* __restrict__ bbox,
                                                          const int32_t ntile, const float escale,
                                                          const float skip_s2, double* __restrict__ r_out,
                                                          float* __restrict__ q_out) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int rt = blockIdx.x * (kBlock / 64) + wave;
-  const int i0 = rt * kRowTileSum;
-  if (i0 >= n) return;
+  const int rt = blockIdx.x;
+  const int i0 = rt * kRowTileSum;  // < n: one block per row tile
   const int i = i0 + lane;
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
@@ -150,6 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rowsum(const float* __restrict
   }
   double acc = 0.0;
   for_near_tiles<DIM>(bbox, ntile, rbox, skip_s2, [&](int t) {
+    if (t % kSumWaves != wave) return;  // another wave's tile
     const int j0 = t * kColTile;
     float a = 0.0f;
     if (j0 + kColTile <= n) {
@@ -170,9 +177,17 @@ __global__ __launch_bounds__(kBlock) void k_dense_rowsum(const float* __restrict
     }
     acc += (double)a;
   });
-  if (valid) {
-    r_out[i] = acc;
-    q_out[i] = (float)(1.0 / acc);
+  __shared__ double part[kSumWaves][64];
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0) {
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < kSumWaves; ++w) r += part[w][lane];
+    if (valid) {
+      r_out[i] = r;
+      q_out[i] = (float)(1.0 / r);
+    }
   }
 }
 
@@ -208,8 +223,10 @@ __global__ __launch_bounds__(kBlock) void k_dense_prep_b(const float* __restrict
   }
 }
 
-// Pass 2: one wave per 16-row tile; lane l generates the 8 weights
-// W[i0 + l%16][32 t + 8 (l/16) + e], the A operand of the MFMA.
+// Pass 2: one block per 16-row tile, its kExWaves waves taking the near column
+// tiles t = wave mod kExWaves; lane l generates the 8 weights
+// W[i0 + l%16][32 t + 8 (l/16) + e], the A operand of the MFMA.  The waves'
+// partial C tiles are added in wave order, and the first wave finishes.
 template <int DIM, int NCB>
 __global__ __launch_bounds__(kBlock) void k_dense_exchange(
     const float* __restrict__ pos, const int64_t cap, const int32_t n, const float* __restrict__ min_,
@@ -218,13 +235,14 @@ __global__ __launch_bounds__(kBlock) void k_dense_exchange(
     const int32_t S, const int32_t react_a, const int32_t react_b, const int32_t norm,
     double* __restrict__ audit_part) {
   constexpr int NC = 16 * NCB;
-  __shared__ double csh[kBlock / 64][kRowTile][NC];
+  static_assert(kExWaves == kBlock / 64, "one block of kExWaves waves per row tile");
+  __shared__ double cpart[kExWaves - 1][NCB * 4][64];
+  __shared__ double csh[kRowTile][NC];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int rt = blockIdx.x * (kBlock / 64) + wave;
+  const int rt = blockIdx.x;
   const int i0 = rt * kRowTile;
-  // waves past the end do no work but still reach the block barrier below
-  const bool active = i0 < n;
+  const bool active = i0 < n;  // always: one block per row tile
   const int ri = lane & 15, kg = lane >> 4;
   const int i = i0 + ri;
   const bool valid_i = i < n;
@@ -242,6 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_exchange(
   load_box<DIM>(bbox, i0 / kColTile, rbox);
 
   for_near_tiles<DIM>(bbox, ntile, rbox, skip_s2, [&](int t) {
+    if (t % kExWaves != wave) return;  // another wave's tile
     const int jb = t * kColTile + 8 * kg;
     float w[8];
 #pragma unroll
@@ -280,17 +299,32 @@ __global__ __launch_bounds__(kBlock) void k_dense_exchange(
     }
   });
   }  // active
+  // the other waves' partial C tiles, added by the first in wave order
+  if (wave > 0) {
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cpart[wave - 1][cb * 4 + e][lane] = acc[cb][e];
+  }
+  __syncthreads();
+  if (wave > 0) return;
+#pragma unroll
+  for (int w = 0; w < kExWaves - 1; ++w)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[cb][e] += cpart[w][cb * 4 + e][lane];
   // C[row 4 kg + e][col] lives in lane (col + 16 kg): gather rows through LDS
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) csh[wave][4 * kg + e][cb * 16 + ri] = acc[cb][e];
-  __syncthreads();
+    for (int e = 0; e < 4; ++e) csh[4 * kg + e][cb * 16 + ri] = acc[cb][e];
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   double tot[9];
 #pragma unroll
   for (int s = 0; s < 9; ++s) tot[s] = 0.0;
   if (active && lane < kRowTile && valid_i) {
-    const double* C = csh[wave][lane];
+    const double* C = csh[lane];
     const double qi = (double)q[i];
     double Mn[8];
 #pragma unroll
@@ -339,13 +373,13 @@ hipError_t launch_dense_step(int dim, const DenseArgs& a, hipStream_t s) {
   const int NC = 16 * a.ncb;
   if (a.ncb < 1 || a.ncb > 2 || dim < 1 || dim > 3) return hipErrorInvalidValue;
   const dim3 gbox((unsigned)((ntile + kBlock - 1) / kBlock));
-  const dim3 gsum((unsigned)((n + kRowTileSum * 4 - 1) / (kRowTileSum * 4)));
-  const dim3 gex((unsigned)((n + kRowTile * 4 - 1) / (kRowTile * 4)));
+  const dim3 gsum((unsigned)((n + kRowTileSum - 1) / kRowTileSum)), bsum(64 * kSumWaves);
+  const dim3 gex((unsigned)((n + kRowTile - 1) / kRowTile));
   const dim3 gprep((unsigned)((a.cap + kBlock - 1) / kBlock));
   auto go = [&](auto d) {
     constexpr int D = decltype(d)::value;
     hipLaunchKernelGGL((k_tile_bbox<D>), gbox, b, 0, s, a.pos, n, a.bbox);
-    hipLaunchKernelGGL((k_dense_rowsum<D>), gsum, b, 0, s, a.pos, n, a.bbox, ntile, a.escale,
+    hipLaunchKernelGGL((k_dense_rowsum<D>), gsum, bsum, 0, s, a.pos, n, a.bbox, ntile, a.escale,
                        a.skip_s2, a.r, a.q);
     hipLaunchKernelGGL(k_dense_prep_b, gprep, b, 0, s, a.mass_in, a.q, a.cap, n, a.S, a.norm, NC, a.bparts);
     if (a.ncb == 1)
