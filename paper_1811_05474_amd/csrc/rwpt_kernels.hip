@@ -1156,7 +1156,11 @@ __device__ __forceinline__ void for_own_rows(const RealParams& P, const StencilR
 // off[q] is <= t.
 template <int DIM>
 struct PrivBatch {
-  static constexpr int kRowBatch = DIM == 1 ? 1 : 4;
+  // two rows at a time in 2-D and 3-D: every iteration waits for the lane with
+  // the longest concatenation, and two shorter ones waste fewer slots than one
+  // of all four rows (8e6 particles in 3-D, steps of 0.655 against 0.660 ms
+  // with four rows; 0.68-0.72 ms with one row at a time)
+  static constexpr int kRowBatch = DIM == 1 ? 1 : 2;
   // six keeps eight waves per SIMD in the binary32 3-D row sum; measured
   // against 2, 3, 4, 8 and 12 at 8e6 particles (225.7 us against 315, 286,
   // 267, 230 and 259)
