@@ -905,12 +905,42 @@ __device__ __forceinline__ void chunk_pick(RowCursor& c, const RealParams& P, co
   }
 }
 
-// Runs compute(load(j, has), act) for every chunk of 64 virtual candidates of
-// every segment of the tile (NPARTS > 1: only chunks part, part + NPARTS, ...;
-// the cursor still walks the others, without loads); `act` marks the lanes
-// whose particle is in the segment.  Software-pipelined: the candidates of the
-// next chunk are picked and their loads issued before the current chunk is
-// computed, so the load latency overlaps the chunk's arithmetic.
+// A segment's last chunk when it holds n <= 32 candidates: lane (g, K) of
+// row g takes candidate g * per + K for K < per (per = 4 for n <= 16, else 8),
+// so that the chunk is evaluated in per broadcast steps instead of 16.  The
+// picked (j, has) of candidate c sits in lane c; every lane takes part in the
+// permutes.  Returns the chunk's step count.
+__device__ __forceinline__ int chunk_compact(const RowCursor& c, uint32_t vbase, int32_t& j, bool& has) {
+  if (c.valid) return 16;
+  const uint32_t n = __builtin_amdgcn_readfirstlane(c.p - vbase);
+  if (n > 32u) return 16;
+  const int per = n > 16u ? 8 : 4;
+  const int lane = threadIdx.x & 63, g = lane >> 4, k = lane & 15;
+  const int src = g * per + k;  // < 64 for every lane
+  const int32_t js = __shfl(j, src);
+  const bool hs = __shfl(has ? 1 : 0, src) != 0;
+  j = js;
+  has = hs && k < per;
+  return per;
+}
+
+// compute(data, act, nk) with the step count nk as a compile-time constant.
+template <typename ComputeFn, typename Data>
+__device__ __forceinline__ void compute_steps(ComputeFn&& compute, const Data& d, bool act, int nk) {
+  if (nk == 16) compute(d, act, std::integral_constant<int, 16>{});
+  else if (nk == 8) compute(d, act, std::integral_constant<int, 8>{});
+  else compute(d, act, std::integral_constant<int, 4>{});
+}
+
+// Runs compute(load(j, has), act, nk) for every chunk of 64 virtual
+// candidates of every segment of the tile (NPARTS > 1: only chunks part, part
+// + NPARTS, ...; the cursor still walks the others, without loads); `act`
+// marks the lanes whose particle is in the segment, nk the chunk's broadcast
+// steps (16, or 8 or 4 for a short last chunk of a whole-tile launch; the
+// split form keeps 16, where the compaction measured slower).  Software-pipelined: the
+// candidates of the next chunk are picked and their loads issued before the
+// current chunk is computed, so the load latency overlaps the chunk's
+// arithmetic.
 template <int NPARTS, typename LoadFn, typename ComputeFn>
 __device__ __forceinline__ void for_tile_chunks(const RealParams& P, const StencilRow* __restrict__ st,
                                                 const uint32_t* __restrict__ cell_start, const TileLane& tl,
@@ -943,6 +973,7 @@ __device__ __forceinline__ void for_tile_chunks(const RealParams& P, const Stenc
     }
     if (c.valid) {
       chunk_pick(c, P, st, cell_start, cy, cz, cxa, cxb, vbase, jdummy, j, has);
+      int nk = NPARTS == 1 ? chunk_compact(c, vbase, j, has) : 16;
       auto cur = load(j, has);
       while (true) {
         if constexpr (NPARTS > 1) {
@@ -953,14 +984,18 @@ __device__ __forceinline__ void for_tile_chunks(const RealParams& P, const Stenc
         }
         const bool next = c.valid;
         decltype(cur) nxt = cur;
+        int nk_next = 16;
         if (next) {
           vbase += 64;
           chunk_pick(c, P, st, cell_start, cy, cz, cxa, cxb, vbase, jdummy, j, has);
+          if constexpr (NPARTS == 1) nk_next = chunk_compact(c, vbase, j, has);
           nxt = load(j, has);
         }
-        compute(cur, act);
+        if constexpr (NPARTS == 1) compute_steps(compute, cur, act, nk);
+        else compute(cur, act, std::integral_constant<int, 16>{});
         if (!next) break;
         cur = nxt;
+        nk = nk_next;
       }
     }
     seg = seg_end;
@@ -997,12 +1032,12 @@ __global__ __launch_bounds__(kBlock) void k_rowsum_dpp(
           d.has = has;
           return d;
         },
-        [&](const Cand& d, bool act) {
+        [&](const Cand& d, bool act, auto nkc) {
           float xj[DIM];
 #pragma unroll
           for (int k = 0; k < DIM; ++k) xj[k] = d.x[k];
           if (!d.has) xj[0] = 3.0e38f;  // s^2 overflows to +inf: outside the cutoff, weight 0
-          acc += (double)rowsum_chunk<DIM>(xj, xi, rc2, esc, act);
+          acc += (double)rowsum_chunk<DIM, decltype(nkc)::value>(xj, xi, rc2, esc, act);
         });
   } else {
     acc = 1.0;
@@ -1068,7 +1103,8 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
           d.has = has;
           return d;
         },
-        [&](const Cand& d, bool act) {
+        [&](const Cand& d, bool act, auto nkc) {
+          constexpr int NK = decltype(nkc)::value;
           float xj[DIM], mj[SMAX];
 #pragma unroll
           for (int k = 0; k < DIM; ++k) xj[k] = d.x[k];
@@ -1080,9 +1116,9 @@ __global__ __launch_bounds__(kBlock) void k_exchange_dpp(
           for (int s = 0; s < SMAX; ++s) accr[s] = 0.0f;
           float rr = 0.0f;
           if (sym) {
-            exchange_chunk_sym<DIM, SMAX>(xj, xi, d.q, qi, mj, Mi, rc2, esc, act, accr);
+            exchange_chunk_sym<DIM, SMAX, NK>(xj, xi, d.q, qi, mj, Mi, rc2, esc, act, accr);
           } else {
-            exchange_chunk_row<DIM, SMAX>(xj, xi, mj, Mi, rc2, esc, act, rr, accr);
+            exchange_chunk_row<DIM, SMAX, NK>(xj, xi, mj, Mi, rc2, esc, act, rr, accr);
           }
 #pragma unroll
           for (int s = 0; s < SMAX; ++s) acc[s] += (double)accr[s];
@@ -1602,14 +1638,14 @@ __global__ __launch_bounds__(kBlock) void k_nbr_dpp(PairArgs a) {
           d.has = has;
           return d;
         },
-        [&](const Cand& d, bool act) {
+        [&](const Cand& d, bool act, auto nkc) {
           float xj[DIM];
 #pragma unroll
           for (int k = 0; k < DIM; ++k) xj[k] = d.x[k];
           if (!d.has) xj[0] = 3.0e38f;
           const float jf = __builtin_bit_cast(float, d.j);
           const float hf = d.has ? 1.0f : 0.0f;
-          Steps<0, 16>::run([&](auto kc) {
+          Steps<0, decltype(nkc)::value>::run([&](auto kc) {
             constexpr int K = decltype(kc)::value;
             // s^2 of the broadcast candidate exactly as row_weight forms it
             const float d0 = rshare<K>(xj[0]) - xi[0];

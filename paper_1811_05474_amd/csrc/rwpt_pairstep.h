@@ -135,12 +135,13 @@ __device__ __forceinline__ float row_weight(const float (&xj)[DIM], const float 
   return (act && s2 <= rc2) ? w : 0.0f;
 }
 
-// Row sum over one chunk: sum over K of w(i, j_K).
-template <int DIM>
+// Row sum over one chunk: sum over K of w(i, j_K).  NK < 16: only the
+// first NK lanes of each row hold candidates (a segment's short last chunk).
+template <int DIM, int NK = 16>
 __device__ __forceinline__ float rowsum_chunk(const float (&xj)[DIM], const float (&xi)[DIM], float rc2, float esc,
                                               bool act) {
   float a = 0.0f;
-  Steps<0, 16>::run([&](auto kc) {
+  Steps<0, NK>::run([&](auto kc) {
     constexpr int K = decltype(kc)::value;
     a += row_weight<K, DIM>(xj, xi, rc2, esc, act);
   });
@@ -150,11 +151,11 @@ __device__ __forceinline__ float rowsum_chunk(const float (&xj)[DIM], const floa
 // Exchange over one chunk, symmetric normalisation: accr[s] += w (q_j + q_i)
 // (m_j[s] - M_i[s]) with q = 1 / r, i.e. twice the symmetric P_ij times the
 // mass difference.
-template <int DIM, int SMAX>
+template <int DIM, int SMAX, int NK = 16>
 __device__ __forceinline__ void exchange_chunk_sym(const float (&xj)[DIM], const float (&xi)[DIM], float qj, float qi,
                                                    const float (&mj)[SMAX], const float (&Mi)[SMAX], float rc2,
                                                    float esc, bool act, float (&accr)[SMAX]) {
-  Steps<0, 16>::run([&](auto kc) {
+  Steps<0, NK>::run([&](auto kc) {
     constexpr int K = decltype(kc)::value;
     const float w = row_weight<K, DIM>(xj, xi, rc2, esc, act);
     const float p = w * (rshare<K>(qj) + qi);  // 2 * symmetric P_ij
@@ -165,11 +166,11 @@ __device__ __forceinline__ void exchange_chunk_sym(const float (&xj)[DIM], const
 
 // Exchange over one chunk, row normalisation: rr += w and accr[s] += w
 // (m_j[s] - M_i[s]); the caller divides by r_i = rr summed over all chunks.
-template <int DIM, int SMAX>
+template <int DIM, int SMAX, int NK = 16>
 __device__ __forceinline__ void exchange_chunk_row(const float (&xj)[DIM], const float (&xi)[DIM],
                                                    const float (&mj)[SMAX], const float (&Mi)[SMAX], float rc2,
                                                    float esc, bool act, float& rr, float (&accr)[SMAX]) {
-  Steps<0, 16>::run([&](auto kc) {
+  Steps<0, NK>::run([&](auto kc) {
     constexpr int K = decltype(kc)::value;
     const float w = row_weight<K, DIM>(xj, xi, rc2, esc, act);
     rr += w;
