@@ -47,9 +47,12 @@ def D_for_neighbours(dim, n, mean_nb, dt=0.1):
 # (dim, n, lanes, mean neighbours): the four-lane row-broadcast tiles with one
 # block per tile (<= 4096 tiles of 16) and with whole tiles per wave; one lane
 # per particle with every lane cached (few neighbours) and most lanes beyond
-# the per-lane cache (many); the vector-load tiles
+# the per-lane cache (many); the vector-load tiles.  Sparse four-lane whole
+# tiles: most segments end in a short chunk of at most 16 or 32 candidates,
+# evaluated in 4 or 8 broadcast steps
 CASES = [
     (1, 32768, 4, 60.0), (1, 80000, 4, 60.0),
+    (1, 80000, 4, 4.0), (2, 80000, 4, 3.0), (2, 80000, 4, 12.0),
     (2, 40000, 4, 200.0), (2, 120000, 4, 200.0),
     (3, 40000, 4, 30.0), (3, 80000, 4, 30.0),
     (1, 30000, -1, 3.0), (2, 30000, -1, 2.5), (2, 30000, -1, 12.0),
