@@ -755,6 +755,35 @@ def test_interface1d_l50_matches_erfc(prec):
     ens.close()
 
 
+# ----------------------------- four-lane whole tiles, short last chunks ----
+
+@pytest.mark.parametrize("dim,mean_nb", [(1, 4.0), (2, 3.0), (2, 12.0), (2, 40.0)])
+@pytest.mark.parametrize("S,norm", [(2, rwpt.RWPT_NORM_SYM), (2, rwpt.RWPT_NORM_ROW), (8, rwpt.RWPT_NORM_SYM)])
+def test_four_lane_whole_tiles_with_short_last_chunks(dim, mean_nb, S, norm):
+    # more than 4096 tiles of 16 (one wave per tile) at few neighbours: most
+    # segments end in a chunk of at most 16 or 32 candidates, evaluated in 4
+    # or 8 broadcast steps; the exchange on identical positions (no walk) must
+    # match the oracle to the binary32 bar after each of two steps
+    n, dt, seed = 80000, 0.1, 7300 + dim
+    unit = {1: 2.0, 2: math.pi}[dim]
+    rc = (mean_nb / ((n - 1) * unit)) ** (1.0 / dim)
+    D = rc * rc / (72.0 * dt)
+    x = f32(W.positions(n, dim, seed))
+    M = f32(W.masses(n, S, seed))
+    ens = make(dim=dim, S=S, prec=F32, norm=norm, seed=seed, lanes=4)
+    ens.init([n], x, M)
+    onorm = oracle.NORM_SYM if norm == rwpt.RWPT_NORM_SYM else oracle.NORM_ROW
+    ref = M
+    for step in range(2):
+        ens.step(dt, D, 1)
+        ref = oracle.transfer(x, ref, D, dt, kappa=3.0, prec=32, norm=onorm, react=(0, 1))
+        check_err(ens.masses(), ref, 1e-5, step)
+    assert ens.stats()["tile_lanes"] == 4 and -(-n // 16) > 4096
+    pairs, evals = ens.count_pairs(dt, D)
+    assert 0.5 * mean_nb * n < pairs < 1.5 * mean_nb * n
+    ens.close()
+
+
 # ------------------------------------- one lane per particle, neighbour cache ----
 
 @pytest.mark.parametrize("dim", [1, 2, 3])
